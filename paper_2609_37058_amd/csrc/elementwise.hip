@@ -1,0 +1,253 @@
+// Memory-bound helpers of the transmission path: block fills (operator
+// formation z S - H, identities, copies with row gathers), the elementwise
+// half of a decimation step, Gamma = i (Sigma - Sigma^+), Frobenius scales
+// and the Caroli trace.  Reductions use a fixed order (per-thread strided
+// sums, then a fixed LDS tree), so results do not depend on the batch a
+// request runs in.
+#include "common.h"
+#include "kernels.h"
+
+namespace rgf {
+namespace {
+
+constexpr int ET = 256;
+
+__global__ __launch_bounds__(ET) void fill_kernel(FillArgs a) {
+  const int b = blockIdx.y;
+  if (a.ctl.skip && a.ctl.skip[b]) return;
+  const int64_t n = (int64_t)a.rows * a.cols;
+  const int64_t e = (int64_t)blockIdx.x * ET + threadIdx.x;
+  if (a.flags && e < a.flags_n) a.flags[(int64_t)b * a.flags_bs + e] = 0;
+  if (e >= n) return;
+  const int r = (int)(e / a.cols), c = (int)(e % a.cols);
+  z64 v;
+  switch (a.kind) {
+    case FILL_IDENTITY: v = zmake(r == c ? a.scale : 0.0, 0.0); break;
+    case FILL_MAT: {
+      z64 s = a.src.p[mat_off(a.src, b, r, c)];
+      v = zmake(a.scale * s.x, a.scale * s.y);
+      break;
+    }
+    case FILL_FORM: {
+      z64 s = form_elem(a.f, b, r, c);
+      v = zmake(a.scale * s.x, a.scale * s.y);
+      break;
+    }
+    default: v = zmake(0.0, 0.0);
+  }
+  a.dst.p[mat_off(a.dst, b, r, c)] = v;
+}
+
+__global__ __launch_bounds__(ET) void axpy_kernel(MatRef dst, MatRef src, double s, int rows, int cols,
+                                                   BatchCtl ctl) {
+  const int b = blockIdx.y;
+  if (ctl.skip && ctl.skip[b]) return;
+  const int64_t e = (int64_t)blockIdx.x * ET + threadIdx.x;
+  if (e >= (int64_t)rows * cols) return;
+  const int r = (int)(e / cols), c = (int)(e % cols);
+  z64 x = src.p[mat_off(src, b, r, c)];
+  z64* d = dst.p + mat_off(dst, b, r, c);
+  *d = zmake(d->x + s * x.x, d->y + s * x.y);
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = ET / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Elementwise half of a decimation step (products already in C):
+//   eps_R -= aXb, eps_L -= bXa, eps -= aXb + bXa, alpha = -aXa, beta = -bXb
+// and the next augmented block [eps | alpha | beta]; partial ||alpha||^2, ||beta||^2.
+constexpr int SR_EPT = 16;
+__global__ __launch_bounds__(ET) void sr_update_kernel(SrUpdateArgs a) {
+  const int b = blockIdx.y;
+  if (a.ctl.skip && a.ctl.skip[b]) return;
+  __shared__ double sh[ET];
+  const int Mp = a.Mp;
+  const int64_t n = (int64_t)Mp * Mp;
+  double sa = 0.0, sb = 0.0;
+  for (int q = 0; q < SR_EPT; ++q) {
+    const int64_t e = ((int64_t)blockIdx.x * SR_EPT + q) * ET + threadIdx.x;
+    if (e >= n) break;
+    const int r = (int)(e / Mp), c = (int)(e % Mp);
+    const z64 aXa = a.C.p[mat_off(a.C, b, r, c)];
+    const z64 aXb = a.C.p[mat_off(a.C, b, r, Mp + c)];
+    const z64 bXa = a.C.p[mat_off(a.C, b, Mp + r, c)];
+    const z64 bXb = a.C.p[mat_off(a.C, b, Mp + r, Mp + c)];
+    z64* pe = a.eps.p + mat_off(a.eps, b, r, c);
+    z64* pl = a.epsL.p + mat_off(a.epsL, b, r, c);
+    z64* pr = a.epsR.p + mat_off(a.epsR, b, r, c);
+    const z64 ne = zsub(zsub(*pe, aXb), bXa);
+    *pe = ne;
+    *pl = zsub(*pl, bXa);
+    *pr = zsub(*pr, aXb);
+    const z64 al = zneg(aXa), be = zneg(bXb);
+    a.AB.p[mat_off(a.AB, b, r, c)] = al;
+    a.AB.p[mat_off(a.AB, b, Mp + r, c)] = be;
+    a.Tsr.p[mat_off(a.Tsr, b, r, c)] = ne;
+    a.Tsr.p[mat_off(a.Tsr, b, r, Mp + c)] = al;
+    a.Tsr.p[mat_off(a.Tsr, b, r, 2 * Mp + c)] = be;
+    if (c == 0) a.flags[(int64_t)b * a.flags_bs + r] = 0;
+    sa += al.x * al.x + al.y * al.y;
+    sb += be.x * be.x + be.y * be.y;
+  }
+  sa = block_sum(sa, sh);
+  sb = block_sum(sb, sh);
+  if (threadIdx.x == 0) {
+    a.partial[((int64_t)b * a.nblk + blockIdx.x) * 2 + 0] = sa;
+    a.partial[((int64_t)b * a.nblk + blockIdx.x) * 2 + 1] = sb;
+  }
+}
+
+__global__ void sr_check_kernel(const double* partial, int nblk, const double* scale, double tol, int it,
+                                int32_t* done, int32_t* iters, int32_t* active_count, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  if (done[b]) return;
+  double sa = 0.0, sb = 0.0;
+  for (int k = 0; k < nblk; ++k) {
+    sa += partial[((int64_t)b * nblk + k) * 2 + 0];
+    sb += partial[((int64_t)b * nblk + k) * 2 + 1];
+  }
+  iters[b] = it;
+  if (sqrt(sa) + sqrt(sb) <= tol * scale[b]) {
+    done[b] = 1;
+  } else {
+    atomicAdd(active_count, 1);
+  }
+}
+
+__global__ __launch_bounds__(ET) void frob_scale_kernel(MatRef X, int rows, int cols, double* scale) {
+  const int b = blockIdx.x;
+  __shared__ double sh[ET];
+  double s = 0.0;
+  const int64_t n = (int64_t)rows * cols;
+  for (int64_t e = threadIdx.x; e < n; e += ET) {
+    const z64 v = X.p[mat_off(X, b, (int)(e / cols), (int)(e % cols))];
+    s += v.x * v.x + v.y * v.y;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) scale[b] = fmax(1.0, sqrt(s));
+}
+
+__global__ __launch_bounds__(ET) void broadening_kernel(MatRef sig, MatRef gam, int Mp) {
+  const int b = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * ET + threadIdx.x;
+  if (e >= (int64_t)Mp * Mp) return;
+  const int r = (int)(e / Mp), c = (int)(e % Mp);
+  const z64 x = sig.p[mat_off(sig, b, r, c)];
+  const z64 y = zconj(sig.p[mat_off(sig, b, c, r)]);
+  gam.p[mat_off(gam, b, r, c)] = zmake(-(x.y - y.y), x.x - y.x);
+}
+
+__global__ __launch_bounds__(ET) void trace_kernel(TraceArgs a) {
+  const int b = blockIdx.x;
+  __shared__ double sh[ET];
+  const int Mp = a.Mp;
+  double s = 0.0;
+  const int64_t n = (int64_t)Mp * Mp;
+  for (int64_t e = threadIdx.x; e < n; e += ET) {
+    const int r = (int)(e / Mp), c = (int)(e % Mp);
+    const z64 x = a.Z1.p[mat_off(a.Z1, b, r, c)];
+    const z64 y = a.Z2.p[mat_off(a.Z2, b, r, c)];
+    s += x.x * y.x + x.y * y.y;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    int32_t info = 0;
+    if (a.sr_done_l && !a.sr_done_l[b]) info |= RGF_INFO_SR_LEFT;
+    if (a.sr_done_r && !a.sr_done_r[b]) info |= RGF_INFO_SR_RIGHT;
+    const int32_t sc = a.sing ? a.sing[b] : 0;
+    if (sc != 0) info |= RGF_INFO_SINGULAR | ((sc - 1) & 0xFFFFFF) << 8;
+    if (sc == 0 && !isfinite(s)) info |= RGF_INFO_NONFINITE;
+    if (info & (RGF_INFO_SINGULAR | RGF_INFO_NONFINITE)) s = __builtin_nan("");
+    a.T[b] = s;
+    if (a.info) a.info[b] = info;
+  }
+}
+
+__global__ __launch_bounds__(ET) void unpad_kernel(MatRef src, z64* dst, int M) {
+  const int b = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * ET + threadIdx.x;
+  if (e >= (int64_t)M * M) return;
+  const int r = (int)(e / M), c = (int)(e % M);
+  dst[(int64_t)b * M * M + e] = src.p[mat_off(src, b, r, c)];
+}
+
+__global__ void sr_info_kernel(const int32_t* done, int32_t bit, const int32_t* sing, int32_t* info,
+                               int batch, int accumulate) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  int32_t v = accumulate ? info[b] : 0;
+  if (!done[b]) v |= bit;
+  if (sing && sing[b] != 0) v |= RGF_INFO_SINGULAR | ((sing[b] - 1) & 0xFFFFFF) << 8;
+  info[b] = v;
+}
+
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + ET - 1) / ET); }
+
+}  // namespace
+
+void launch_fill(const FillArgs& a, int batch, hipStream_t st) {
+  if (batch <= 0) return;
+  const int64_t n = std::max<int64_t>((int64_t)a.rows * a.cols, a.flags ? a.flags_n : 0);
+  hipLaunchKernelGGL(fill_kernel, dim3(nblocks(n), batch), dim3(ET), 0, st, a);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_axpy(MatRef dst, MatRef src, double s, int rows, int cols, int batch, BatchCtl ctl,
+                 hipStream_t st) {
+  if (batch <= 0) return;
+  hipLaunchKernelGGL(axpy_kernel, dim3(nblocks((int64_t)rows * cols), batch), dim3(ET), 0, st, dst, src, s,
+                     rows, cols, ctl);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_sr_update(const SrUpdateArgs& a, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(sr_update_kernel, dim3(a.nblk, batch), dim3(ET), 0, st, a);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_sr_check(const double* partial, int nblk, const double* scale, double tol, int it,
+                     int32_t* done, int32_t* iters, int32_t* active_count, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(sr_check_kernel, dim3((batch + 127) / 128), dim3(128), 0, st, partial, nblk, scale, tol,
+                     it, done, iters, active_count, batch);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_frob_scale(MatRef X, int rows, int cols, double* scale, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(frob_scale_kernel, dim3(batch), dim3(ET), 0, st, X, rows, cols, scale);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_broadening(MatRef sigma, MatRef gamma, int Mp, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(broadening_kernel, dim3(nblocks((int64_t)Mp * Mp), batch), dim3(ET), 0, st, sigma,
+                     gamma, Mp);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_trace(const TraceArgs& a, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(trace_kernel, dim3(batch), dim3(ET), 0, st, a);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_unpad(MatRef src, z64* dst, int M, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(unpad_kernel, dim3(nblocks((int64_t)M * M), batch), dim3(ET), 0, st, src, dst, M);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_sr_info(const int32_t* done, int32_t bit, const int32_t* sing, int32_t* info, int batch,
+                    int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL(sr_info_kernel, dim3((batch + 127) / 128), dim3(128), 0, st, done, bit, sing, info,
+                     batch, accumulate);
+  RGF_HIP(hipGetLastError());
+}
+
+}  // namespace rgf

@@ -1,0 +1,77 @@
+// Host-side driver of the batched transmission path (one chunk of energies).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace rgf {
+
+constexpr double SR_TOL = 1e-14;
+constexpr int SR_MAXIT = 100;
+constexpr int32_t SING_LEAD = 0x1000000;  // stored code; decodes to layer field 0xFFFFFF
+
+struct Profiler;
+Profiler& profiler();
+void profile_launch_begin(hipStream_t st);
+void profile_launch_end(hipStream_t st, double flops);
+bool profiling();
+
+int tile_for(int prec);
+
+// Device memory for `batch` energies at padded block size Mp.
+struct Layout {
+  int Mp = 0, batch = 0;
+  int nblk_sr = 0;
+  size_t bytes = 0;
+  // offsets (bytes) into the arena
+  size_t sig, un, R, scr, mult, perm, flags, ints, dbl;
+  static Layout make(int Mp, int batch);
+};
+
+class Engine {
+ public:
+  Engine(char* arena, const Layout& lay, hipStream_t st, int prec, int M, const double* E, double eta,
+         int32_t* host_active);
+
+  // decimation of `lead` for all energies of the chunk; leaves eps_L, eps_R
+  void decimate(const rgf_lead& lead, int32_t* done);
+  // sigma = L (eps_L^-1 U) for the left side, U (eps_R^-1 L) for the right side
+  void self_energy(const rgf_lead& lead, bool left, z64* out);
+  // Gamma_L, Gamma_R from Sigma_L, Sigma_R
+  void broadenings();
+  // recursive sweep over the device, then the Caroli trace into T/info
+  void sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool same_leads);
+  // lead-only output: copy sigma into the caller's dense [batch][M][M]
+  void export_sigma(z64* sigma_ws, rgf_z* out);
+  void lead_info(int side_bit, int32_t* done, int32_t* info);
+
+  z64* sigL() { return sigL_; }
+  z64* sigR() { return sigR_; }
+  int32_t* done_l() { return done_l_; }
+  int32_t* done_r() { return done_r_; }
+  void reset_flags();
+
+ private:
+  MatRef mref(z64* p, int64_t ld, int64_t bstride, const int32_t* ridx = nullptr) const;
+  void gje_prec(z64* T, int W, int64_t bs, const int32_t* skip, int32_t code, int prec);
+  double gemm(GemmArgs g, int prec, bool timed);
+
+  hipStream_t st_;
+  int prec_, M_, Mp_, B_;
+  const double* E_;
+  double eta_;
+  int64_t MM_;
+  int nblk_sr_;
+  z64 *sigL_, *sigR_, *gamL_, *gamR_;
+  z64 *eps_, *epsL_, *epsR_, *AB_, *C_, *Tsr_;
+  z64 *Taug_, *Wa_, *Wb_, *P_, *Z1_, *Z2_;
+  z64 *R_, *scr_, *mult_;
+  int32_t *perm_, *done_l_, *done_r_, *iters_, *sing_, *active_;
+  uint8_t* flags_;
+  double *scale_, *partial_;
+  int32_t* host_active_;
+};
+
+}  // namespace rgf

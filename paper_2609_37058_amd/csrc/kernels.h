@@ -1,0 +1,149 @@
+// Kernel argument blocks and launchers of librgf (host + device declarations).
+#pragma once
+
+#include "common.h"
+
+namespace rgf {
+
+// ---------------------------------------------------------------- small path
+struct SmallArgs {
+  int N, M;
+  const z64 *Hd, *Hu, *Sd, *Su;
+  const z64 *LH00, *LH01, *LS00, *LS01;
+  const z64 *RH00, *RH01, *RS00, *RS01;
+  int same_leads;
+  const double* E;
+  int64_t nE;
+  double eta;
+  double* T;
+  int32_t* info;
+  double sr_tol;
+  int sr_maxit;
+};
+constexpr int SMALL_MAX_M = 16;
+void launch_small(const SmallArgs& a, hipStream_t st);
+
+// ---------------------------------------------------------- block products
+// C[b] = Cin[b] + alpha * opA[b] * opB[b], complex, for rows x cols outputs
+// with inner dimension K (all multiples of the tile).  opA is a per-batch
+// matrix or a formed operator block; opB is a per-batch matrix (optionally
+// row-gathered); Cin is none, a per-batch matrix or a formed block.
+enum { SRC_NONE = 0, SRC_MAT = 1, SRC_FORM = 2 };
+enum { PREC_F64 = 0, PREC_F32 = 1 };
+
+struct GemmArgs {
+  int rows, cols, K, batch;
+  int a_kind;
+  MatRef A;
+  FormRef Af;
+  MatRef B;
+  int c_kind;
+  MatRef Cin;
+  FormRef Cf;
+  MatRef C;
+  double alpha;
+  BatchCtl ctl;
+};
+
+// tile = 64 or 128 (square output tiles); role 1 marks the sweep's main block
+// products (a separate kernel symbol, so profiles can single them out).
+// Returns the algorithmic flops launched.
+double launch_gemm(const GemmArgs& g, int prec, int tile, hipStream_t st, int role = 0);
+
+// ------------------------------------------------- Gauss-Jordan elimination
+constexpr int GJE_NB = 64;
+struct PanelArgs {
+  MatRef T;  // augmented [B | RHS]; Mp rows; ld = width W
+  int Mp;
+  int W;
+  int k0;
+  z64* scratch;
+  int64_t scratch_bs;  // Mp x 64 per batch
+  z64* mult;
+  int64_t mult_bs;  // Mp x 64 per batch: elimination multipliers
+  z64* prow;
+  int64_t prow_bs;  // 64 x W per batch (ld W): pivot rows right of the panel
+  int32_t* perm;
+  int64_t perm_bs;  // Mp per batch
+  uint8_t* flags;
+  int64_t flags_bs;  // Mp per batch
+  int32_t* sing;     // per batch: first singular event code (0 = none)
+  int32_t sing_code;
+  BatchCtl ctl;
+};
+void launch_gje_panel(const PanelArgs& a, int batch, hipStream_t st);
+
+// Buffers of a batched Gauss-Jordan solve (per batch: P 64 x 3Mp, scratch Mp x 64,
+// mult Mp x 64, perm Mp, flags Mp; sing 1).
+struct GjeBufs {
+  z64* P;
+  z64* scr;
+  z64* mult;
+  int32_t* perm;
+  uint8_t* flags;
+  int32_t* sing;
+};
+// Solve on T = [B | RHS] (Mp x W per batch, batch stride bs, flags already zero):
+// afterwards row perm[c] of the RHS columns holds row c of B^-1 RHS.  The block
+// products of the elimination run in `prec`; pivoting and the pivot-block
+// inverses are always FP64.  `timed` marks the products for the profiler.
+void gje_solve(const GjeBufs& g, z64* T, int W, int64_t bs, int Mp, int batch, const int32_t* skip,
+               int32_t code, int prec, int tile, hipStream_t st);
+
+// ---------------------------------------------------------- elementwise
+enum { FILL_ZERO = 0, FILL_IDENTITY = 1, FILL_MAT = 2, FILL_FORM = 3 };
+struct FillArgs {
+  MatRef dst;  // rows x cols block
+  int rows, cols;
+  int kind;
+  double scale;  // multiplies the source (identity: the diagonal value)
+  MatRef src;
+  FormRef f;
+  uint8_t* flags;  // optional: zeroed (Mp per batch) -- reset of pivot flags
+  int64_t flags_bs;
+  int flags_n;
+  BatchCtl ctl;
+};
+void launch_fill(const FillArgs& a, int batch, hipStream_t st);
+
+// dst[b] += s * src[b] (rows x cols)
+void launch_axpy(MatRef dst, MatRef src, double s, int rows, int cols, int batch, BatchCtl ctl,
+                 hipStream_t st);
+
+struct SrUpdateArgs {
+  int Mp;
+  MatRef C;      // 2Mp x 2Mp products [aXa aXb; bXa bXb]
+  MatRef eps, epsL, epsR;
+  MatRef AB;     // 2Mp x Mp: alpha over beta
+  MatRef Tsr;    // Mp x 3Mp: next [eps | alpha | beta]
+  uint8_t* flags;
+  int64_t flags_bs;
+  double* partial;  // per batch: gridDim.x blocks x 2 sums of squares
+  int nblk;
+  BatchCtl ctl;
+};
+void launch_sr_update(const SrUpdateArgs& a, int batch, hipStream_t st);
+// per batch: sqrt-sums of partials vs tol*scale -> done/iters; counts still-active batches
+void launch_sr_check(const double* partial, int nblk, const double* scale, double tol, int it,
+                     int32_t* done, int32_t* iters, int32_t* active_count, int batch, hipStream_t st);
+// per batch: scale[b] = max(1, ||X[b]||_F) over rows x cols
+void launch_frob_scale(MatRef X, int rows, int cols, double* scale, int batch, hipStream_t st);
+// gamma[b] = i (sigma[b] - sigma[b]^+), Mp x Mp
+void launch_broadening(MatRef sigma, MatRef gamma, int Mp, int batch, hipStream_t st);
+// T[b] = Re sum Z1 .* conj(Z2); info composition; NaN on singular/nonfinite
+struct TraceArgs {
+  MatRef Z1, Z2;
+  int Mp;
+  double* T;
+  int32_t* info;
+  const int32_t* sr_done_l;  // decimation converged flags (1 = converged) of left/right
+  const int32_t* sr_done_r;
+  const int32_t* sing;       // per batch singular code (0 = none)
+};
+void launch_trace(const TraceArgs& a, int batch, hipStream_t st);
+// copy sigma (Mp-padded workspace) into a dense [batch][M][M] user buffer, and info bits
+void launch_unpad(MatRef src, z64* dst, int M, int batch, hipStream_t st);
+void launch_sr_info(const int32_t* done, int32_t bit, const int32_t* sing, int32_t* info, int batch,
+                    int accumulate, hipStream_t st);
+
+}  // namespace rgf

@@ -1,0 +1,216 @@
+"""Python binding of librgf (ctypes): argument marshalling only.
+
+Every step of the transmission path runs in the HIP library; this module
+only turns torch tensors (device memory) and streams into the C-ABI
+structs of ``include/rgf.h``.  It raises if the library is missing: there
+is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librgf.so")
+
+RGF_FP64, RGF_MIXED = 0, 1
+RGF_LEFT, RGF_RIGHT = 0, 1
+RGF_OK, RGF_EINVAL, RGF_ENOMEM, RGF_EDEVICE, RGF_EAGAIN, RGF_ETOOBIG, RGF_ENOTICKET = 0, -1, -2, -3, -4, -5, -6
+INFO_SR_LEFT, INFO_SR_RIGHT, INFO_SINGULAR, INFO_NONFINITE = 1, 2, 4, 8
+PRECISION = {"fp64": RGF_FP64, "mixed": RGF_MIXED, RGF_FP64: RGF_FP64, RGF_MIXED: RGF_MIXED}
+
+
+class RgfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"librgf error {code}: {msg}")
+        self.code = code
+
+
+class rgf_lead(C.Structure):
+    _fields_ = [("M", C.c_int32), ("H00", C.c_void_p), ("H01", C.c_void_p), ("S00", C.c_void_p),
+                ("S01", C.c_void_p)]
+
+
+class rgf_device(C.Structure):
+    _fields_ = [("N", C.c_int32), ("M", C.c_int32), ("Hd", C.c_void_p), ("Hu", C.c_void_p),
+                ("Sd", C.c_void_p), ("Su", C.c_void_p), ("left", rgf_lead), ("right", rgf_lead)]
+
+
+class rgf_server_opts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("lead_cache_bytes", C.c_uint64), ("max_slots", C.c_int32)]
+
+
+class rgf_server_stats(C.Structure):
+    _fields_ = [("finished", C.c_uint64), ("cache_hits", C.c_uint64), ("cache_misses", C.c_uint64),
+                ("peak_inflight_bytes", C.c_uint64), ("cache_bytes", C.c_uint64)]
+
+
+_lib = None
+
+#: every symbol include/rgf.h declares, with (restype, argtypes)
+SIGNATURES = {
+    "rgf_transmission": (C.c_int, [C.POINTER(rgf_device), C.c_void_p, C.c_int64, C.c_double, C.c_int,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lead_self_energy": (C.c_int, [C.POINTER(rgf_lead), C.c_int, C.c_void_p, C.c_int64, C.c_double, C.c_int,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]),
+    "transport_open": (C.c_int, [C.POINTER(rgf_server_opts), C.POINTER(C.c_void_p)]),
+    "transport_submit": (C.c_int, [C.c_void_p, C.POINTER(rgf_device), C.c_uint64, C.c_uint64, C.c_void_p,
+                                   C.c_int64, C.c_double, C.c_int, C.POINTER(C.c_uint64)]),
+    "transport_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "transport_close": (C.c_int, [C.c_void_p]),
+    "transport_stats": (C.c_int, [C.c_void_p, C.POINTER(rgf_server_stats)]),
+    "rgf_last_error": (C.c_char_p, []),
+    "rgf_version": (C.c_char_p, []),
+    "rgf_release_workspaces": (C.c_int, []),
+    "rgf_profile": (C.c_int, [C.c_int]),
+    "rgf_profile_read": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "rgf_get_tile": (C.c_int, [C.c_int, C.POINTER(C.c_int32)]),
+    "rgf_set_tile": (C.c_int, [C.c_int, C.c_int32]),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load librgf.so (built in-tree by ``paper_2609_37058_amd.build``); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2609_37058_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != RGF_OK:
+        raise RgfError(rc, load().rgf_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("librgf takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+@dataclass
+class LeadTensors:
+    """One lead principal layer on the device (complex128 M x M each)."""
+    H00: torch.Tensor
+    H01: torch.Tensor
+    S00: torch.Tensor
+    S01: torch.Tensor
+
+    @property
+    def M(self) -> int:
+        return self.H00.shape[-1]
+
+    def cstruct(self) -> rgf_lead:
+        return rgf_lead(self.M, _ptr(self.H00), _ptr(self.H01), _ptr(self.S00), _ptr(self.S01))
+
+
+@dataclass
+class DeviceTensors:
+    """A block-tridiagonal device on the GPU: Hd, Sd [N, M, M]; Hu, Su [N-1, M, M] (complex128)."""
+    Hd: torch.Tensor
+    Hu: torch.Tensor
+    Sd: torch.Tensor
+    Su: torch.Tensor
+    left: LeadTensors
+    right: LeadTensors
+
+    @property
+    def N(self) -> int:
+        return self.Hd.shape[0]
+
+    @property
+    def M(self) -> int:
+        return self.Hd.shape[-1]
+
+    def cstruct(self) -> rgf_device:
+        hu = _ptr(self.Hu) if self.Hu.numel() else None
+        su = _ptr(self.Su) if self.Su.numel() else None
+        return rgf_device(self.N, self.M, _ptr(self.Hd), hu, _ptr(self.Sd), su,
+                          self.left.cstruct(), self.right.cstruct())
+
+
+def transmission(dev: DeviceTensors, E: torch.Tensor, eta: float, precision="fp64", stream=None,
+                 out: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None
+                 ) -> Tuple[torch.Tensor, torch.Tensor]:
+    """T(E) for every energy in E (float64 device tensor); returns (T, info) device tensors.
+
+    Stream-ordered like the C call: synchronise the stream before reading T.
+    """
+    lib = load()
+    E = E.contiguous()
+    nE = E.numel()
+    if out is None:
+        out = torch.empty(nE, dtype=torch.float64, device=E.device)
+    if info is None:
+        info = torch.empty(nE, dtype=torch.int32, device=E.device)
+    d = dev.cstruct()
+    _check(lib.rgf_transmission(C.byref(d), _ptr(E), nE, float(eta), PRECISION[precision], _ptr(out),
+                                _ptr(info), _stream(stream)))
+    return out, info
+
+
+def lead_self_energy(lead: LeadTensors, side: int, E: torch.Tensor, eta: float, precision="fp64",
+                     stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Sigma[nE, M, M] of one lead (side RGF_LEFT: L g_L U, RGF_RIGHT: U g_R L) and info."""
+    lib = load()
+    E = E.contiguous()
+    nE = E.numel()
+    sigma = torch.empty((nE, lead.M, lead.M), dtype=torch.complex128, device=E.device)
+    info = torch.empty(nE, dtype=torch.int32, device=E.device)
+    ls = lead.cstruct()
+    _check(lib.lead_self_energy(C.byref(ls), int(side), _ptr(E), nE, float(eta), PRECISION[precision],
+                                _ptr(sigma), _ptr(info), _stream(stream)))
+    return sigma, info
+
+
+def release_workspaces():
+    _check(load().rgf_release_workspaces())
+
+
+def profile(enable: bool):
+    _check(load().rgf_profile(1 if enable else 0))
+
+
+def profile_read() -> Tuple[int, float, float]:
+    """(launches, total kernel ms, total algorithmic flops) of the sweep's main block products."""
+    n = C.c_int64()
+    ms = C.c_double()
+    fl = C.c_double()
+    _check(load().rgf_profile_read(C.byref(n), C.byref(ms), C.byref(fl)))
+    return n.value, ms.value, fl.value
+
+
+def get_tile(precision="fp64") -> int:
+    t = C.c_int32()
+    _check(load().rgf_get_tile(PRECISION[precision], C.byref(t)))
+    return t.value
+
+
+def set_tile(precision, tile: int):
+    _check(load().rgf_set_tile(PRECISION[precision], int(tile)))
+
+
+def version() -> str:
+    return load().rgf_version().decode()

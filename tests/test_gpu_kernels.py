@@ -1,0 +1,82 @@
+"""Single-kernel checks on the GPU through the test-only harness library.
+
+The block product is compared with a plain product computed on the CPU
+(complex128 numpy); the Gauss-Jordan solve with ``numpy.linalg.solve``.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+from gpu_helpers import log
+
+pytestmark = pytest.mark.gpu
+
+KT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                  "paper_2609_37058_amd", "librgf_ktest.so")
+
+
+@pytest.fixture(scope="module")
+def kt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lib = C.CDLL(KT)
+    lib.rgf_ktest_gemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_double, C.c_int]
+    lib.rgf_ktest_gje.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]
+    return lib
+
+
+def _rand(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("prec,tile", [(0, 64), (1, 64), (1, 128), (0, 128)])
+@pytest.mark.parametrize("rows,cols,K,batch", [(64, 64, 16, 1), (128, 64, 64, 3), (128, 256, 48, 2)])
+def test_gemm_matches_numpy(kt, prec, tile, rows, cols, K, batch):
+    import torch
+    if tile == 128 and (rows % 128 or cols % 128):
+        pytest.skip("shape not tiled by 128")
+    rng = np.random.default_rng(rows + cols + K + batch)
+    A = _rand(rng, (batch, rows, K))
+    B = _rand(rng, (batch, K, cols))
+    C0 = _rand(rng, (batch, rows, cols))
+    ta, tb, tc = (torch.as_tensor(x).cuda() for x in (A, B, C0))
+    log(f"[kernel] gemm prec={prec} tile={tile} {rows}x{cols}x{K} b={batch}")
+    rc = kt.rgf_ktest_gemm(prec, tile, rows, cols, K, batch, ta.data_ptr(), tb.data_ptr(), tc.data_ptr(),
+                           -1.0, 1)
+    assert rc == 0
+    got = tc.cpu().numpy()
+    ref = C0 - A @ B
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    log(f"[kernel] gemm rel err {err:.2e}")
+    assert err < (1e-14 if prec == 0 else 2e-6)
+
+
+@pytest.mark.parametrize("Mp,nrhs,batch", [(64, 64, 2), (128, 128, 3), (192, 384, 2), (256, 256, 1)])
+def test_gje_matches_numpy_solve(kt, Mp, nrhs, batch):
+    import torch
+    rng = np.random.default_rng(Mp + nrhs)
+    Bm = _rand(rng, (batch, Mp, Mp))
+    # rows scaled so that partial pivoting must reorder them
+    Bm *= np.exp(rng.uniform(-3, 3, size=(batch, Mp, 1)))
+    R = _rand(rng, (batch, Mp, nrhs))
+    T = np.concatenate([Bm, R], axis=2)
+    tt = torch.as_tensor(np.ascontiguousarray(T)).cuda()
+    X = torch.zeros((batch, Mp, nrhs), dtype=torch.complex128, device="cuda")
+    perm = np.zeros((batch, Mp), np.int32)
+    sing = np.zeros(batch, np.int32)
+    log(f"[kernel] gje Mp={Mp} nrhs={nrhs} b={batch}")
+    rc = kt.rgf_ktest_gje(0, Mp, Mp + nrhs, batch, tt.data_ptr(), X.data_ptr(), perm.ctypes.data,
+                          sing.ctypes.data)
+    assert rc == 0
+    got = X.cpu().numpy()
+    ref = np.linalg.solve(Bm, R)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    log(f"[kernel] gje rel err {err:.2e}; perm is a permutation: {all(sorted(p) == list(range(Mp)) for p in perm)}")
+    assert all(sorted(p) == list(range(Mp)) for p in perm)
+    assert np.all(sing == 0)
+    assert err < 1e-10
