@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the transmission hot path: energy-point x layers per second at block size 1024.
+
+Workload (default): the doped-channel device beyond 10,000 atoms -- 400
+principal layers of M = 1024 orbitals, complex128 blocks (25 GiB on the
+GPU), 512 energies on [-2, 2] eV, eta = 1e-6.  One step is one full pass
+of the path over a batch of energies from that grid: decimation of the
+lead for every energy, self-energies, the recursive sweep over all 400
+layers and the Caroli trace.  Nothing is cached between steps.  Inputs are
+resident in HBM before the timed region; staging is not timed.
+
+Prints one JSON line (see the keys below).  The FP64 path is the headline
+``value``; the mixed path is measured beside it with --precision both.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
+METRIC = "RGF energy-point*layers/s at block 1024 (FP64 vs mixed); p50/p99 solve latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--energies-per-step", type=int, default=128)
+    ap.add_argument("--layers", type=int, default=400, help="principal layers (400 = the full workload)")
+    ap.add_argument("--block", type=int, default=1024, help="block size M (1024 = the full workload)")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="fp64")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="block-product tile (64/128); 0 = library default")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, budget_s: float):
+    """The FP64 oracle, as it stands, timed on the host on a bounded sample of the workload.
+
+    Sample: one energy of the grid (the middle one) through ``oracle.transmission``
+    on the first n layers of the same device (same principal layer, same
+    dopants, same leads): lead decimation, self-energies, block-Thomas
+    elimination and back-substitution, Caroli trace.  n is sized so the run
+    takes about ``budget_s`` seconds; the rate is n / wall time, in the
+    benchmark's unit (energy-point x layers per second, decimation included).
+    """
+    from threadpoolctl import threadpool_info
+    import oracle
+    import synth
+
+    dev = cfg.device
+    E = float(cfg.energies[len(cfg.energies) // 2])
+    # about 0.4 s per layer and 10 s of decimation at M = 1024 on 8 cores; scale as M^3
+    scale = (dev.M / 1024.0) ** 3
+    n = int(max(2, min(dev.N, (budget_s - 10.0 * scale) / max(0.4 * scale, 1e-3))))
+    sub = synth.Device(n, dev.M, dev.left, dev.right, base=dev.base,
+                       shifts={k: v for k, v in dev.shifts.items() if k < n}, name=dev.name + f"-first{n}")
+    t0 = time.perf_counter()
+    oracle.transmission(sub, [E], cfg.eta, method="thomas")
+    wall = time.perf_counter() - t0
+    threads = max((p.get("num_threads", 1) for p in threadpool_info()), default=1)
+    return {
+        "value": n / wall,
+        "unit": "energy-point*layers/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"oracle.transmission (numpy/scipy FP64, block-Thomas) on 1 energy (E={E:.4f} eV) "
+                   f"and the first {n} of {dev.N} layers of the workload device, decimation included; "
+                   f"{wall:.1f} s wall"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (one process, one MI355X); --gpus {args.gpus} is not supported. "
+              "The path shards over energies with no exchange during compute; see the design notes.",
+              file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    import synth
+    from paper_2609_37058_amd import rgf, staging
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev_name = torch.cuda.get_device_name(0)
+    cfg = synth.config_c4(n_e=512) if (args.layers == 400 and args.block == 1024) else \
+        synth.config_doped(4, 404, args.layers, args.block, 512, f"c4-N{args.layers}-M{args.block}")
+    d = cfg.device
+    print(f"[bench] staging {cfg.name}: N={d.N} M={d.M} on {dev_name}", file=sys.stderr, flush=True)
+    b = d.base
+    dev_t = staging.stage_repeated(b.H00, b.H01, b.S00, b.S01, d.N, d.shifts)
+    E_all = torch.as_tensor(cfg.energies).cuda()
+    nE = len(cfg.energies)
+    B = min(args.energies_per_step, nE)
+    if args.tile:
+        rgf.set_tile("fp64", args.tile)
+        rgf.set_tile("mixed", args.tile)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    results = {}
+    for prec in precisions:
+        def step(k):
+            lo = (k * B) % nE
+            Eb = E_all[lo:lo + B]
+            if Eb.numel() < B:
+                Eb = torch.cat([Eb, E_all[:B - Eb.numel()]])
+            return rgf.transmission(dev_t, Eb, cfg.eta, prec)
+
+        for k in range(args.warmup):
+            print(f"[bench] {prec} warmup step {k}", file=sys.stderr, flush=True)
+            T, info = step(k)
+        torch.cuda.synchronize()
+        rgf.profile(True)
+        rgf.profile_read()
+        lat = []
+        infos = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            T, info = step(args.warmup + k)
+            ev1.record(stream)
+            infos.append(info)
+            ev1.synchronize()
+            lat.append(ev0.elapsed_time(ev1) / 1e3)
+            print(f"[bench] {prec} step {k}: {lat[-1]:.2f} s", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        n_launch, k_ms, k_flops = rgf.profile_read()
+        rgf.profile(False)
+        bad = int(sum(int((i != 0).sum().item()) for i in infos))
+        wall = t1 - t0
+        results[prec] = {
+            "value": args.steps * B * d.N / wall,
+            "ms_per_step": wall / args.steps * 1e3,
+            "lat": lat,
+            "kernel": {"launches": n_launch, "ms": k_ms, "flops": k_flops},
+            "nonzero_info": bad,
+        }
+
+    head = results["fp64"] if "fp64" in results else results[precisions[0]]
+    hp = "fp64" if "fp64" in results else precisions[0]
+    kr = head["kernel"]
+    peak = FP64_MFMA_PEAK_TFLOPS if hp == "fp64" else FP32_MFMA_PEAK_TFLOPS
+    achieved = (kr["flops"] / (kr["ms"] / 1e3) / 1e12) if kr["ms"] > 0 else None
+    lat = np.array(head["lat"])
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "energy-point*layers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if hp == "fp64" else "f32-mfma+f64",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "layers": d.N, "block": d.M, "energies_per_step": B,
+                   "energy_grid": f"linspace(-2,2,{nE})", "eta": cfg.eta, "precision": hp,
+                   "dopant_layers": len(d.shifts)},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "sweep block product (zgemm role 1)",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": (achieved / peak) if achieved else None,
+            "traffic": None,
+            "launches": kr["launches"],
+            "avg_launch_ms": kr["ms"] / max(1, kr["launches"]),
+        },
+        "nonzero_info": head["nonzero_info"],
+    }
+    if "mixed" in results and "fp64" in results:
+        m = results["mixed"]
+        out["mixed"] = {"value": m["value"], "ms_per_step": m["ms_per_step"],
+                        "speedup_vs_fp64": m["value"] / results["fp64"]["value"]}
+    if not args.no_cpu_baseline:
+        print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
