@@ -10,17 +10,19 @@
 // load brings both parts of an element, and the LDS tiles keep them
 // interleaved so one LDS read feeds the real and the imaginary MFMA.  The
 // FP64 path uses v_mfma_f64_16x16x4 (16x16 output block, K = 4 per
-// instruction; its output rows are interleaved by 4 across registers); the FP32 path converts operands to float when they are
-// staged into LDS and uses v_mfma_f32_16x16x4 with FP32 accumulation.
-// Operator blocks z S - H (and z S^+ - H^+) are formed while staging, so
-// the energy-dependent operands are never written to HBM.
+// instruction; its output rows are interleaved by 4 across registers);
+// the FP32 path converts operands to float when they are staged into LDS
+// and uses v_mfma_f32_16x16x4 with FP32 accumulation.  Operator blocks
+// z S - H (and z S^+ - H^+) are formed while staging, so the
+// energy-dependent operands are never written to HBM.
 //
-// Work split: 256 threads = 4 wavefronts in a 2x2 grid, each owning a
-// (TILE/2) x (TILE/2) output block; K advances 16 complex columns per LDS
-// stage with the next stage's global loads issued before the current
-// stage's MFMAs.  Tiles are handed out so that each of the 8 XCDs works on
-// a contiguous range of (batch, row-tile, col-tile) ids: the operands of
-// one batch entry stay in one XCD's L2.
+// Work split: a BM x BN output tile per workgroup of WGM x WGN wavefronts,
+// each wavefront owning a (BM/WGM) x (BN/WGN) block of 16x16 MFMA tiles.
+// K advances 16 complex columns per LDS stage; the next stage's global
+// loads are issued before the current stage's MFMAs, so HBM/L2 latency
+// hides behind the (64-cycle) FP64 MFMAs.  Tiles are handed out so that
+// each of the 8 XCDs works on a contiguous range of (batch, row-tile,
+// col-tile) ids: the operands of one batch entry stay in one XCD's L2.
 #include "common.h"
 #include "kernels.h"
 
@@ -31,7 +33,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 16;
-constexpr int GT = 256;
 
 template <typename R>
 struct CT;
@@ -58,23 +59,20 @@ struct CT<float> {
   __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-// Element (r, k) of opA for batch b.
-__device__ inline z64 load_a_mat(const GemmArgs& g, int b, int r, int k) {
-  return g.A.p[mat_off(g.A, b, r, k)];
-}
-
-template <typename R, int TILE, int ROLE>
-__global__ __launch_bounds__(GT) void zgemm_kernel(GemmArgs g, int tiles_m, int tiles_n) {
+template <typename R, int BM, int BN, int WGM, int WGN, int ROLE>
+__global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   typedef typename CT<R>::c cR;
   typedef typename CT<R>::acc accT;
-  constexpr int PAD = 1;
-  constexpr int LDT = TILE + PAD;
-  constexpr int WT = TILE / 2;  // wave tile
-  constexpr int F = WT / 16;    // 16x16 blocks per wave dimension
-  constexpr int EPT = TILE * BK / GT;  // staged elements per thread per operand
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  constexpr int EA = BM * BK / NT;  // staged A elements per thread
+  constexpr int EB = BK * BN / NT;  // staged B elements per thread
+  constexpr int LDA = BM + 1, LDB = BN + 1;
+  static_assert(EA >= 1 && EB >= 1 && BK % EA == 0 && BN % EB == 0 && BM % EA == 0, "tile split");
 
-  __shared__ cR As[BK * LDT];
-  __shared__ cR Bs[BK * LDT];
+  __shared__ cR As[BK * LDA];
+  __shared__ cR Bs[BK * LDB];
 
   // ---- tile id, XCD-aware ----
   const int64_t total = (int64_t)tiles_m * tiles_n * g.batch;
@@ -89,110 +87,113 @@ __global__ __launch_bounds__(GT) void zgemm_kernel(GemmArgs g, int tiles_m, int 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int row0 = tm * TILE, col0 = tn * TILE;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int row0 = tm * BM, col0 = tn * BN;
 
-  accT accr[F][F], acci[F][F];
+  accT accr[FM][FN], acci[FM][FN];
 #pragma unroll
-  for (int i = 0; i < F; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < F; ++j) {
+    for (int j = 0; j < FN; ++j) {
       accr[i][j] = accT{0, 0, 0, 0};
       acci[i][j] = accT{0, 0, 0, 0};
     }
 
-  z64 ra[EPT], rb[EPT];
-  const z64 zz = (g.a_kind == SRC_FORM) ? zmake(g.Af.E[b], g.Af.eta) : zmake(0.0, 0.0);
+  // ---- A staging: row-major map (BK/EA threads per row) or k-major (conj_t forms) ----
+  const bool a_form = g.a_kind == SRC_FORM;
+  const bool a_ct = a_form && g.Af.conj_t;
+  int a_r, a_k;  // this thread's first element of the A tile
+  if (a_ct) {
+    a_k = tid / (BM / EA);
+    a_r = (tid % (BM / EA)) * EA;
+  } else {
+    a_r = tid / (BK / EA);
+    a_k = (tid % (BK / EA)) * EA;
+  }
+  const z64* a_ptr = nullptr;  // MAT: element (a_r, a_k) at k0 = 0
+  const z64 *a_s = nullptr, *a_h = nullptr;
+  int a_M = 0;
+  z64 zz = zmake(0.0, 0.0);
+  if (a_form) {
+    a_M = g.Af.M;
+    a_s = g.Af.S;
+    a_h = g.Af.H;
+    zz = zmake(g.Af.E[b], g.Af.eta);
+  } else {
+    a_ptr = g.A.p + mat_off(g.A, b, row0 + a_r, a_k);
+  }
+  // ---- B staging: k-major map ----
+  const int b_k = tid / (BN / EB);
+  const int b_c = (tid % (BN / EB)) * EB;
+  const z64* b_base = g.B.p + b * g.B.bstride + col0 + b_c;
+  const int32_t* b_ridx = g.B.rowidx ? g.B.rowidx + (int64_t)b * g.B.ridx_bstride : nullptr;
 
-  // staging maps: "row-major" (4 threads x 4 elements per 16-wide row) and
-  // "k-major" (16 threads x 4 elements along a TILE-wide row)
-  auto load_a = [&](int k0) {
-    if (g.a_kind == SRC_FORM && g.Af.conj_t) {
+  z64 ra[EA], rb[EB];
+  auto load = [&](int k0) {
+    if (!a_form) {
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int idx = tid + e * GT;
-        const int k = idx / TILE, r = idx % TILE;
-        const int gr = row0 + r, gk = k0 + k;
+      for (int e = 0; e < EA; ++e) ra[e] = a_ptr[k0 + e];
+    } else if (a_ct) {
+      const int gk = k0 + a_k;
+#pragma unroll
+      for (int e = 0; e < EA; ++e) {
+        const int gr = row0 + a_r + e;
         z64 v = zmake(0.0, 0.0);
-        if (gr < g.Af.M && gk < g.Af.M) {
-          z64 s = g.Af.S[(int64_t)gk * g.Af.M + gr];
-          z64 h = g.Af.H[(int64_t)gk * g.Af.M + gr];
-          v = zform(zz, zconj(s), zconj(h));
+        if (gr < a_M && gk < a_M) {
+          const int64_t o = (int64_t)gk * a_M + gr;
+          v = zform(zz, zconj(a_s[o]), zconj(a_h[o]));
         }
         ra[e] = v;
       }
     } else {
+      const int gr = row0 + a_r;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int idx = tid + e * GT;
-        const int r = idx / BK, k = idx % BK;
-        const int gr = row0 + r, gk = k0 + k;
-        z64 v;
-        if (g.a_kind == SRC_FORM) {
-          v = zmake(0.0, 0.0);
-          if (gr < g.Af.M && gk < g.Af.M)
-            v = zform(zz, g.Af.S[(int64_t)gr * g.Af.M + gk], g.Af.H[(int64_t)gr * g.Af.M + gk]);
-        } else {
-          v = load_a_mat(g, b, gr, gk);
+      for (int e = 0; e < EA; ++e) {
+        const int gk = k0 + a_k + e;
+        z64 v = zmake(0.0, 0.0);
+        if (gr < a_M && gk < a_M) {
+          const int64_t o = (int64_t)gr * a_M + gk;
+          v = zform(zz, a_s[o], a_h[o]);
         }
         ra[e] = v;
       }
     }
-  };
-  auto store_a = [&]() {
-    if (g.a_kind == SRC_FORM && g.Af.conj_t) {
+    const int kr = k0 + b_k;
+    const int64_t brow = b_ridx ? (int64_t)b_ridx[kr] : (int64_t)kr;
+    const z64* bp = b_base + brow * g.B.ld;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int idx = tid + e * GT;
-        As[(idx / TILE) * LDT + idx % TILE] = CT<R>::cvt(ra[e]);
-      }
+    for (int e = 0; e < EB; ++e) rb[e] = bp[e];
+  };
+  auto store = [&]() {
+    if (a_ct) {
+#pragma unroll
+      for (int e = 0; e < EA; ++e) As[a_k * LDA + a_r + e] = CT<R>::cvt(ra[e]);
     } else {
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int idx = tid + e * GT;
-        As[(idx % BK) * LDT + idx / BK] = CT<R>::cvt(ra[e]);
-      }
+      for (int e = 0; e < EA; ++e) As[(a_k + e) * LDA + a_r] = CT<R>::cvt(ra[e]);
     }
-  };
-  auto load_b = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int idx = tid + e * GT;
-      const int k = idx / TILE, c = idx % TILE;
-      rb[e] = g.B.p[mat_off(g.B, b, k0 + k, col0 + c)];
-    }
-  };
-  auto store_b = [&]() {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int idx = tid + e * GT;
-      Bs[(idx / TILE) * LDT + idx % TILE] = CT<R>::cvt(rb[e]);
-    }
+    for (int e = 0; e < EB; ++e) Bs[b_k * LDB + b_c + e] = CT<R>::cvt(rb[e]);
   };
 
-  load_a(0);
-  load_b(0);
+  load(0);
   for (int k0 = 0; k0 < g.K; k0 += BK) {
     __syncthreads();
-    store_a();
-    store_b();
+    store();
     __syncthreads();
-    if (k0 + BK < g.K) {
-      load_a(k0 + BK);
-      load_b(k0 + BK);
-    }
+    if (k0 + BK < g.K) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      cR af[F], bf[F];
+      cR af[FM], bf[FN];
 #pragma unroll
-      for (int i = 0; i < F; ++i) af[i] = As[kr * LDT + wm * WT + i * 16 + (lane & 15)];
+      for (int i = 0; i < FM; ++i) af[i] = As[kr * LDA + wm * WTM + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < F; ++j) bf[j] = Bs[kr * LDT + wn * WT + j * 16 + (lane & 15)];
+      for (int j = 0; j < FN; ++j) bf[j] = Bs[kr * LDB + wn * WTN + j * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < F; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < F; ++j) {
+        for (int j = 0; j < FN; ++j) {
           accr[i][j] = CT<R>::mfma(af[i].x, bf[j].x, accr[i][j]);
           accr[i][j] = CT<R>::mfma(-af[i].y, bf[j].y, accr[i][j]);
           acci[i][j] = CT<R>::mfma(af[i].x, bf[j].y, acci[i][j]);
@@ -204,13 +205,13 @@ __global__ __launch_bounds__(GT) void zgemm_kernel(GemmArgs g, int tiles_m, int 
   // ---- epilogue: C = Cin + alpha * acc ----
   const z64 zc = (g.c_kind == SRC_FORM) ? zmake(g.Cf.E[b], g.Cf.eta) : zmake(0.0, 0.0);
 #pragma unroll
-  for (int i = 0; i < F; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < F; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = row0 + wm * WT + i * 16 + CT<R>::out_row(lane, v);
-        const int c = col0 + wn * WT + j * 16 + (lane & 15);
+        const int r = row0 + wm * WTM + i * 16 + CT<R>::out_row(lane, v);
+        const int c = col0 + wn * WTN + j * 16 + (lane & 15);
         z64 out = zmake(g.alpha * (double)accr[i][j][v], g.alpha * (double)acci[i][j][v]);
         if (g.c_kind == SRC_MAT) {
           out = zadd(out, g.Cin.p[mat_off(g.Cin, b, r, c)]);
@@ -230,14 +231,26 @@ __global__ __launch_bounds__(GT) void zgemm_kernel(GemmArgs g, int tiles_m, int 
       }
 }
 
-template <typename R, int TILE>
-void launch_t(const GemmArgs& g, hipStream_t st, int role) {
-  const int tm = g.rows / TILE, tn = g.cols / TILE;
+template <typename R, int BM, int BN, int WGM, int WGN>
+void launch_cfg(const GemmArgs& g, hipStream_t st, int role) {
+  const int tm = g.rows / BM, tn = g.cols / BN;
   const int64_t total = (int64_t)tm * tn * g.batch;
+  constexpr int NT = 64 * WGM * WGN;
   if (role == 1)
-    hipLaunchKernelGGL((zgemm_kernel<R, TILE, 1>), dim3((unsigned)total), dim3(GT), 0, st, g, tm, tn);
+    hipLaunchKernelGGL((zgemm_kernel<R, BM, BN, WGM, WGN, 1>), dim3((unsigned)total), dim3(NT), 0, st, g, tm, tn);
   else
-    hipLaunchKernelGGL((zgemm_kernel<R, TILE, 0>), dim3((unsigned)total), dim3(GT), 0, st, g, tm, tn);
+    hipLaunchKernelGGL((zgemm_kernel<R, BM, BN, WGM, WGN, 0>), dim3((unsigned)total), dim3(NT), 0, st, g, tm, tn);
+}
+
+template <typename R>
+void launch_prec(const GemmArgs& g, int tile, hipStream_t st, int role) {
+  if (tile >= 128 && g.rows % 128 == 0 && g.cols % 128 == 0) {
+    launch_cfg<R, 128, 128, 2, 4>(g, st, role);
+  } else if (tile >= 128 && g.cols % 128 == 0) {
+    launch_cfg<R, 64, 128, 1, 4>(g, st, role);
+  } else {
+    launch_cfg<R, 64, 64, 2, 2>(g, st, role);
+  }
 }
 
 }  // namespace
@@ -245,15 +258,9 @@ void launch_t(const GemmArgs& g, hipStream_t st, int role) {
 double launch_gemm(const GemmArgs& g, int prec, int tile, hipStream_t st, int role) {
   if (g.rows <= 0 || g.cols <= 0 || g.batch <= 0) return 0.0;
   RGF_CHECK(g.K % BK == 0, RGF_EINVAL, "gemm: K not a multiple of 16");
-  if (tile == 128 && (g.rows % 128 || g.cols % 128)) tile = 64;
-  RGF_CHECK(g.rows % tile == 0 && g.cols % tile == 0, RGF_EINVAL, "gemm: shape not tiled");
-  if (prec == PREC_F64) {
-    if (tile == 128) launch_t<double, 128>(g, st, role);
-    else launch_t<double, 64>(g, st, role);
-  } else {
-    if (tile == 128) launch_t<float, 128>(g, st, role);
-    else launch_t<float, 64>(g, st, role);
-  }
+  RGF_CHECK(g.rows % 64 == 0 && g.cols % 64 == 0, RGF_EINVAL, "gemm: shape not tiled");
+  if (prec == PREC_F64) launch_prec<double>(g, tile, st, role);
+  else launch_prec<float>(g, tile, st, role);
   RGF_HIP(hipGetLastError());
   return 8.0 * g.rows * (double)g.cols * g.K * g.batch;
 }

@@ -27,10 +27,10 @@
 // rather than T[r, K] A_KK^-1 (equal in exact arithmetic): the latter would
 // multiply their rounding errors by the condition number of A_KK.
 //
-// Step 1 holds a 16-column sub-panel of each row in registers (thread per
-// row; 8 columns and two rows per thread when Mp = 2048), applies the rank-16
-// update of the remaining panel columns from LDS-resident pivot rows, and
-// keeps the partially eliminated panel in a per-batch scratch block.
+// Step 1 holds an 8-column sub-panel of each row in registers (thread per
+// row, or two rows per thread when Mp = 2048), applies the rank-8 update of
+// the remaining panel columns from LDS-resident pivot rows, and keeps the
+// partially eliminated panel in a per-batch scratch block.
 #include "common.h"
 #include "kernels.h"
 
@@ -39,6 +39,7 @@ namespace {
 
 constexpr int NB = GJE_NB;
 constexpr int MAXMP = 2048;
+constexpr int MC = 8;  // multiplier columns per register chunk
 
 // In-place Gauss-Jordan inverse of an NB x NB block in LDS, no pivoting.
 __device__ void lds_invert(z64* A, z64* colj, int tid, int nt) {
@@ -240,17 +241,17 @@ __global__ __launch_bounds__(1024) void gje_panel_kernel(PanelArgs a) {
     z64* mrow = mult + (int64_t)r * NB;
     const z64* in = (kind == 1) ? Tb + (int64_t)r * ld + k0 : mrow;
     const z64* Mx = (kind == 0) ? Lf : U;
-    for (int c0 = 0; c0 < NB; c0 += 16) {
-      z64 acc[16];
+    for (int c0 = 0; c0 < NB; c0 += MC) {
+      z64 acc[MC];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) acc[c] = zmake(0.0, 0.0);
+      for (int c = 0; c < MC; ++c) acc[c] = zmake(0.0, 0.0);
       if (kind != 2) {
         // candidates: L11^-1 is lower triangular, so only m >= c0 contributes
         const int m0 = (kind == 0) ? c0 : 0;
         for (int m = m0; m < NB; ++m) {
           const z64 x = in[m];
 #pragma unroll
-          for (int c = 0; c < 16; ++c) acc[c] = zfma(x, Mx[m * NB + c0 + c], acc[c]);
+          for (int c = 0; c < MC; ++c) acc[c] = zfma(x, Mx[m * NB + c0 + c], acc[c]);
         }
       }
       if (kind == 2) {
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(1024) void gje_panel_kernel(PanelArgs a) {
         for (int q = 0; q < NB; ++q)
           if (piv[q] == r) j = q;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
+        for (int c = 0; c < MC; ++c) {
           const z64 w = U[j * NB + c0 + c];
           acc[c] = zmake((c0 + c == j ? 1.0 : 0.0) - w.x, -w.y);
         }
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(1024) void gje_panel_kernel(PanelArgs a) {
       // chunks go left to right and chunk c0 reads columns >= c0 only, so a
       // candidate's l_r can be overwritten in place
 #pragma unroll
-      for (int c = 0; c < 16; ++c) mrow[c0 + c] = acc[c];
+      for (int c = 0; c < MC; ++c) mrow[c0 + c] = acc[c];
     }
   }
   __syncthreads();
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(1024) void gje_panel_kernel(PanelArgs a) {
 void launch_gje_panel(const PanelArgs& a, int batch, hipStream_t st) {
   RGF_CHECK(a.Mp % 64 == 0 && a.Mp <= MAXMP, RGF_EINVAL, "panel: Mp must be a multiple of 64, <= 2048");
   if (a.Mp <= 1024) {
-    hipLaunchKernelGGL((gje_panel_kernel<1, 16>), dim3(batch), dim3(a.Mp), 0, st, a);
+    hipLaunchKernelGGL((gje_panel_kernel<1, 8>), dim3(batch), dim3(a.Mp), 0, st, a);
   } else {
     hipLaunchKernelGGL((gje_panel_kernel<2, 8>), dim3(batch), dim3(1024), 0, st, a);
   }
