@@ -70,7 +70,7 @@ void profile_launch_end(hipStream_t st, double flops) {
 }
 
 // ------------------------------------------------------------- tile config
-static int g_tile[2] = {64, 128};
+static int g_tile[2] = {128, 128};
 int tile_for(int prec) { return g_tile[prec == PREC_F64 ? 0 : 1]; }
 
 // -------------------------------------------------------------- workspaces

@@ -20,16 +20,17 @@ __global__ __launch_bounds__(ET) void fill_kernel(FillArgs a) {
   if (a.flags && e < a.flags_n) a.flags[(int64_t)b * a.flags_bs + e] = 0;
   if (e >= n) return;
   const int r = (int)(e / a.cols), c = (int)(e % a.cols);
+  const int rs = a.ridx ? a.ridx[(int64_t)b * a.ridx_bs + r] : r;
   z64 v;
   switch (a.kind) {
-    case FILL_IDENTITY: v = zmake(r == c ? a.scale : 0.0, 0.0); break;
+    case FILL_IDENTITY: v = zmake(rs == c ? a.scale : 0.0, 0.0); break;
     case FILL_MAT: {
       z64 s = a.src.p[mat_off(a.src, b, r, c)];
       v = zmake(a.scale * s.x, a.scale * s.y);
       break;
     }
     case FILL_FORM: {
-      z64 s = form_elem(a.f, b, r, c);
+      z64 s = form_elem(a.f, b, rs, c);
       v = zmake(a.scale * s.x, a.scale * s.y);
       break;
     }
@@ -64,7 +65,7 @@ __device__ inline double block_sum(double v, double* sh) {
 
 // Elementwise half of a decimation step (products already in C):
 //   eps_R -= aXb, eps_L -= bXa, eps -= aXb + bXa, alpha = -aXa, beta = -bXb
-// and the next augmented block [eps | alpha | beta]; partial ||alpha||^2, ||beta||^2.
+// and the partial sums ||alpha||^2, ||beta||^2 of this block.
 constexpr int SR_EPT = 16;
 __global__ __launch_bounds__(ET) void sr_update_kernel(SrUpdateArgs a) {
   const int b = blockIdx.y;
@@ -91,10 +92,6 @@ __global__ __launch_bounds__(ET) void sr_update_kernel(SrUpdateArgs a) {
     const z64 al = zneg(aXa), be = zneg(bXb);
     a.AB.p[mat_off(a.AB, b, r, c)] = al;
     a.AB.p[mat_off(a.AB, b, Mp + r, c)] = be;
-    a.Tsr.p[mat_off(a.Tsr, b, r, c)] = ne;
-    a.Tsr.p[mat_off(a.Tsr, b, r, Mp + c)] = al;
-    a.Tsr.p[mat_off(a.Tsr, b, r, 2 * Mp + c)] = be;
-    if (c == 0) a.flags[(int64_t)b * a.flags_bs + r] = 0;
     sa += al.x * al.x + al.y * al.y;
     sb += be.x * be.x + be.y * be.y;
   }

@@ -26,7 +26,7 @@ struct Layout {
   int nblk_sr = 0;
   size_t bytes = 0;
   // offsets (bytes) into the arena
-  size_t sig, un, R, scr, mult, perm, flags, ints, dbl;
+  size_t sig, un, linv, uinv, perm, cand, flags, ints, dbl;
   static Layout make(int Mp, int batch);
 };
 
@@ -51,11 +51,10 @@ class Engine {
   z64* sigR() { return sigR_; }
   int32_t* done_l() { return done_l_; }
   int32_t* done_r() { return done_r_; }
-  void reset_flags();
 
  private:
   MatRef mref(z64* p, int64_t ld, int64_t bstride, const int32_t* ridx = nullptr) const;
-  void gje_prec(z64* T, int W, int64_t bs, const int32_t* skip, int32_t code, int prec);
+  FillArgs fill_args(MatRef dst, int rows, int cols, int kind) const;
   double gemm(GemmArgs g, int prec, bool timed);
 
   hipStream_t st_;
@@ -65,11 +64,10 @@ class Engine {
   int64_t MM_;
   int nblk_sr_;
   z64 *sigL_, *sigR_, *gamL_, *gamR_;
-  z64 *eps_, *epsL_, *epsR_, *AB_, *C_, *Tsr_;
-  z64 *Taug_, *Wa_, *Wb_, *P_, *Z1_, *Z2_;
-  z64 *R_, *scr_, *mult_;
-  int32_t *perm_, *done_l_, *done_r_, *iters_, *sing_, *active_;
-  uint8_t* flags_;
+  z64 *eps_, *epsL_, *epsR_, *AB_, *C_, *Tsr_, *Ysr_;
+  z64 *T_, *Y_, *Wa_, *Wb_, *P_, *Z1_, *Z2_;
+  LuBufs lu_;
+  int32_t *done_l_, *done_r_, *iters_, *sing_, *active_;
   double *scale_, *partial_;
   int32_t* host_active_;
 };

@@ -2,23 +2,23 @@
 // energies (all launches stream-ordered on one HIP stream).
 //
 // Per energy the path is (z = E + i eta, A = z S - H, blocks padded to Mp):
-//   decimation   eps [Xa Xb] = [alpha beta] by blocked Gauss-Jordan, then the
-//                four products [alpha; beta] [Xa Xb] in one matrix-core launch
-//                and the elementwise update; repeated until
+//   decimation   eps [Xa Xb] = [alpha beta] (LU of eps, two block triangular
+//                solves), then the four products [alpha; beta] [Xa Xb] in one
+//                matrix-core launch and the elementwise update; repeated until
 //                ||alpha||_F + ||beta||_F <= 1e-14 max(1, ||D||_F)
 //   self-energy  Sigma_L = L_L (eps_L^-1 U_L), Sigma_R = U_R (eps_R^-1 L_R)
 //   sweep        B_0 = A_00 - Sigma_L; for l = 0..N-2:
-//                  X = B_l^-1 U_l                (Gauss-Jordan on [B_l | U_l])
+//                  X = B_l^-1 U_l                (LU of B_l, solves)
 //                  W = X (l = 0), else W <- -W X
 //                  B_{l+1} = A_{l+1} - L_{l+1} X (- Sigma_R on the last layer)
-//                G_1N = -W B_{N-1}^-1             (Gauss-Jordan on [B | I])
+//                G_1N = -W B_{N-1}^-1
 //   trace        T = Re sum (Gamma_L G_1N) .* conj(G_1N Gamma_R)
 // This is the first-row-propagator recursion of the recursive Green's
 // function method written with solves instead of explicit inverses: per
-// point-layer it costs one elimination of [B | U] (12 M^3 real flops as
-// Gauss-Jordan) and two block products (16 M^3), against 40 M^3 when every
-// g_i is inverted and multiplied out.  No per-layer state is kept beyond
-// B, X and W, so the memory per energy does not grow with N.
+// point-layer it costs an LU (8/3 M^3 real flops), two triangular solves
+// with M right-hand sides (8 M^3) and two block products (16 M^3), against
+// 40 M^3 when every g_i is inverted and multiplied out.  No per-layer state
+// is kept beyond B, X and W, so memory per energy does not grow with N.
 #include <algorithm>
 
 #include "engine.h"
@@ -44,10 +44,10 @@ Layout Layout::make(int Mp, int batch) {
   const size_t Z = sizeof(z64);
   l.sig = take(4 * batch * MM * Z);
   l.un = take(12 * batch * MM * Z);
-  l.R = take((size_t)batch * 64 * 3 * Mp * Z);
-  l.scr = take((size_t)batch * Mp * 64 * Z);
-  l.mult = take((size_t)batch * Mp * 64 * Z);
+  l.linv = take((size_t)batch * 64 * Mp * Z);
+  l.uinv = take((size_t)batch * 64 * Mp * Z);
   l.perm = take((size_t)batch * Mp * 4);
+  l.cand = take((size_t)batch * Mp * 4);
   l.flags = take((size_t)batch * Mp);
   l.ints = take((size_t)(4 * batch + 64) * 4);
   l.dbl = take((size_t)(batch + batch * l.nblk_sr * 2) * 8);
@@ -71,27 +71,30 @@ Engine::Engine(char* arena, const Layout& lay, hipStream_t st, int prec, int M, 
   eps_ = un;
   epsL_ = un + U;
   epsR_ = un + 2 * U;
-  AB_ = un + 3 * U;   // per batch 2 MM
-  C_ = un + 5 * U;    // per batch 4 MM
-  Tsr_ = un + 9 * U;  // per batch 3 MM
+  AB_ = un + 3 * U;    // per batch 2 MM
+  C_ = un + 5 * U;     // per batch 4 MM
+  Tsr_ = un + 9 * U;   // per batch MM
+  Ysr_ = un + 10 * U;  // per batch 2 MM
   // sweep view of the same region (used after both self-energies exist)
-  Taug_ = un;         // per batch 2 MM
+  T_ = un;
+  Y_ = un + U;
   Wa_ = un + 2 * U;
   Wb_ = un + 3 * U;
   P_ = un + 4 * U;
   Z1_ = un + 5 * U;
   Z2_ = un + 6 * U;
-  R_ = reinterpret_cast<z64*>(arena + lay.R);
-  scr_ = reinterpret_cast<z64*>(arena + lay.scr);
-  mult_ = reinterpret_cast<z64*>(arena + lay.mult);
-  perm_ = reinterpret_cast<int32_t*>(arena + lay.perm);
-  flags_ = reinterpret_cast<uint8_t*>(arena + lay.flags);
+  lu_.linv = reinterpret_cast<z64*>(arena + lay.linv);
+  lu_.uinv = reinterpret_cast<z64*>(arena + lay.uinv);
+  lu_.perm = reinterpret_cast<int32_t*>(arena + lay.perm);
+  lu_.cand = reinterpret_cast<int32_t*>(arena + lay.cand);
+  lu_.flags = reinterpret_cast<uint8_t*>(arena + lay.flags);
   int32_t* ints = reinterpret_cast<int32_t*>(arena + lay.ints);
   done_l_ = ints;
   done_r_ = ints + B_;
   iters_ = ints + 2 * B_;
   sing_ = ints + 3 * B_;
   active_ = ints + 4 * B_;
+  lu_.sing = sing_;
   double* dbl = reinterpret_cast<double*>(arena + lay.dbl);
   scale_ = dbl;
   partial_ = dbl + B_;
@@ -133,7 +136,7 @@ static GemmArgs gemm_args(int rows, int cols, int K, int batch) {
   return g;
 }
 
-static FillArgs fill_args(MatRef dst, int rows, int cols, int kind) {
+FillArgs Engine::fill_args(MatRef dst, int rows, int cols, int kind) const {
   FillArgs f;
   f.dst = dst;
   f.rows = rows;
@@ -145,17 +148,15 @@ static FillArgs fill_args(MatRef dst, int rows, int cols, int kind) {
   f.flags = nullptr;
   f.flags_bs = 0;
   f.flags_n = 0;
+  f.ridx = nullptr;
+  f.ridx_bs = 0;
   f.ctl.skip = nullptr;
   return f;
 }
 
-void Engine::gje_prec(z64* T, int W, int64_t bs, const int32_t* skip, int32_t code, int prec) {
-  GjeBufs g{R_, scr_, mult_, perm_, flags_, sing_};
-  gje_solve(g, T, W, bs, Mp_, B_, skip, code, prec, tile_for(prec), st_);
-}
-
 void Engine::decimate(const rgf_lead& lead, int32_t* done) {
   const int Mp = Mp_;
+  const int tile = tile_for(PREC_F64);
   RGF_HIP(hipMemsetAsync(done, 0, sizeof(int32_t) * B_, st_));
   RGF_HIP(hipMemsetAsync(iters_, 0, sizeof(int32_t) * B_, st_));
   // eps = eps_L = eps_R = D (identity padding), alpha = U, beta = L
@@ -173,26 +174,27 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done) {
   f.dst = mref(AB_ + MM_, Mp, 2 * MM_);
   f.f.conj_t = 1;
   launch_fill(f, B_, st_);
-  // [eps | alpha | beta]
-  f = fill_args(mref(Tsr_, 3 * Mp, 3 * MM_), Mp, Mp, FILL_MAT);
-  f.src = mref(eps_, Mp, MM_);
-  f.flags = flags_;
-  f.flags_bs = Mp;
-  f.flags_n = Mp;
-  launch_fill(f, B_, st_);
-  f = fill_args(mref(Tsr_ + Mp, 3 * Mp, 3 * MM_), Mp, Mp, FILL_MAT);
-  f.src = mref(AB_, Mp, 2 * MM_);
-  launch_fill(f, B_, st_);
-  f.dst = mref(Tsr_ + 2 * Mp, 3 * Mp, 3 * MM_);
-  f.src = mref(AB_ + MM_, Mp, 2 * MM_);
-  launch_fill(f, B_, st_);
   launch_frob_scale(mref(eps_, Mp, MM_), M_, M_, scale_, B_, st_);
 
   for (int it = 1; it <= SR_MAXIT; ++it) {
-    gje_prec(Tsr_, 3 * Mp, 3 * MM_, done, SING_LEAD, PREC_F64);
+    // [Xa Xb] = eps^-1 [alpha beta]
+    FillArgs c = fill_args(mref(Tsr_, Mp, MM_), Mp, Mp, FILL_MAT);
+    c.src = mref(eps_, Mp, MM_);
+    c.ctl.skip = done;
+    launch_fill(c, B_, st_);
+    lu_factor(lu_, Tsr_, MM_, Mp, B_, done, SING_LEAD, PREC_F64, tile, st_);
+    c = fill_args(mref(Ysr_, 2 * Mp, 2 * MM_), Mp, Mp, FILL_MAT);
+    c.src = mref(AB_, Mp, 2 * MM_, lu_.perm);
+    c.ctl.skip = done;
+    launch_fill(c, B_, st_);
+    c.dst = mref(Ysr_ + Mp, 2 * Mp, 2 * MM_);
+    c.src = mref(AB_ + MM_, Mp, 2 * MM_, lu_.perm);
+    launch_fill(c, B_, st_);
+    lu_solve(lu_, Tsr_, MM_, Mp, Ysr_, 2 * MM_, 2 * Mp, B_, done, PREC_F64, tile, st_);
+    // the four products [alpha; beta] [Xa Xb]
     GemmArgs g = gemm_args(2 * Mp, 2 * Mp, Mp, B_);
     g.A = mref(AB_, Mp, 2 * MM_);
-    g.B = mat(Tsr_ + Mp, 3 * MM_, 3 * Mp, perm_, Mp);
+    g.B = mref(Ysr_, 2 * Mp, 2 * MM_);
     g.C = mref(C_, 2 * Mp, 4 * MM_);
     g.ctl.skip = done;
     gemm(g, PREC_F64, false);
@@ -203,9 +205,6 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done) {
     u.epsL = mref(epsL_, Mp, MM_);
     u.epsR = mref(epsR_, Mp, MM_);
     u.AB = mref(AB_, Mp, 2 * MM_);
-    u.Tsr = mref(Tsr_, 3 * Mp, 3 * MM_);
-    u.flags = flags_;
-    u.flags_bs = Mp;
     u.partial = partial_;
     u.nblk = nblk_sr_;
     u.ctl.skip = done;
@@ -222,23 +221,22 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done) {
 
 void Engine::self_energy(const rgf_lead& lead, bool left, z64* out) {
   const int Mp = Mp_;
-  // [eps_S | RHS] in the last third of the union region (decimation data stays intact)
-  z64* T = Tsr_;
-  const int64_t bs = 3 * MM_;
-  FillArgs f = fill_args(mref(T, 2 * Mp, bs), Mp, Mp, FILL_MAT);
+  const int tile = tile_for(PREC_F64);
+  FillArgs f = fill_args(mref(Tsr_, Mp, MM_), Mp, Mp, FILL_MAT);
   f.src = mref(left ? epsL_ : epsR_, Mp, MM_);
-  f.flags = flags_;
-  f.flags_bs = Mp;
-  f.flags_n = Mp;
   launch_fill(f, B_, st_);
-  f = fill_args(mref(T + Mp, 2 * Mp, bs), Mp, Mp, FILL_FORM);
+  lu_factor(lu_, Tsr_, MM_, Mp, B_, nullptr, SING_LEAD, PREC_F64, tile, st_);
+  // RHS: U of the lead (left side) or L (right side), rows gathered by the pivots
+  f = fill_args(mref(Ysr_, Mp, 2 * MM_), Mp, Mp, FILL_FORM);
   f.f = form(lead.H01, lead.S01, M_, /*conj_t=*/!left, false, E_, eta_);
+  f.ridx = lu_.perm;
+  f.ridx_bs = Mp;
   launch_fill(f, B_, st_);
-  gje_prec(T, 2 * Mp, bs, nullptr, SING_LEAD, PREC_F64);
+  lu_solve(lu_, Tsr_, MM_, Mp, Ysr_, 2 * MM_, Mp, B_, nullptr, PREC_F64, tile, st_);
   GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
   g.a_kind = SRC_FORM;
   g.Af = form(lead.H01, lead.S01, M_, /*conj_t=*/left, false, E_, eta_);
-  g.B = mat(T + Mp, bs, 2 * Mp, perm_, Mp);
+  g.B = mref(Ysr_, Mp, 2 * MM_);
   g.C = mref(out, Mp, MM_);
   gemm(g, PREC_F64, false);
 }
@@ -251,13 +249,13 @@ void Engine::broadenings() {
 void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool same_leads) {
   const int Mp = Mp_;
   const int64_t M2 = (int64_t)M_ * M_;
-  const int64_t bs = 2 * MM_;
   const int N = d.N;
-  MatRef X = mat(Taug_ + Mp, bs, 2 * Mp, perm_, Mp);
-  const int sweep_prec = prec_;
+  const int sp = prec_;
+  const int tile = tile_for(sp);
+  const MatRef X = mref(Y_, Mp, MM_);
 
   // B_0 = A_00 - Sigma_L (- Sigma_R when N = 1)
-  FillArgs f = fill_args(mref(Taug_, 2 * Mp, bs), Mp, Mp, FILL_FORM);
+  FillArgs f = fill_args(mref(T_, Mp, MM_), Mp, Mp, FILL_FORM);
   f.f = form(d.Hd, d.Sd, M_, false, true, E_, eta_);
   f.f.sub = mref(sigL_, Mp, MM_);
   f.f.sub_sign = -1.0;
@@ -265,18 +263,19 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
   if (N == 1) {
     BatchCtl none;
     none.skip = nullptr;
-    launch_axpy(mref(Taug_, 2 * Mp, bs), mref(sigR_, Mp, MM_), -1.0, Mp, Mp, B_, none, st_);
+    launch_axpy(mref(T_, Mp, MM_), mref(sigR_, Mp, MM_), -1.0, Mp, Mp, B_, none, st_);
   }
   z64* Wcur = Wa_;
   z64* Wnxt = Wb_;
   for (int l = 0; l + 1 < N; ++l) {
-    f = fill_args(mref(Taug_ + Mp, 2 * Mp, bs), Mp, Mp, FILL_FORM);
+    // X = B_l^-1 U_l
+    lu_factor(lu_, T_, MM_, Mp, B_, nullptr, l + 1, sp, tile, st_);
+    f = fill_args(mref(Y_, Mp, MM_), Mp, Mp, FILL_FORM);
     f.f = form(d.Hu + l * M2, d.Su + l * M2, M_, false, false, E_, eta_);
-    f.flags = flags_;
-    f.flags_bs = Mp;
-    f.flags_n = Mp;
+    f.ridx = lu_.perm;
+    f.ridx_bs = Mp;
     launch_fill(f, B_, st_);
-    gje_prec(Taug_, 2 * Mp, bs, nullptr, l + 1, sweep_prec);
+    lu_solve(lu_, T_, MM_, Mp, Y_, MM_, Mp, B_, nullptr, sp, tile, st_);
     if (l == 0) {
       FillArgs c = fill_args(mref(Wcur, Mp, MM_), Mp, Mp, FILL_MAT);
       c.src = X;
@@ -287,9 +286,10 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
       g.B = X;
       g.C = mref(Wnxt, Mp, MM_);
       g.alpha = -1.0;
-      gemm(g, sweep_prec, true);
+      gemm(g, sp, true);
       std::swap(Wcur, Wnxt);
     }
+    // B_{l+1} = A_{l+1} - L_{l+1} X (- Sigma_R on the last layer)
     GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
     g.a_kind = SRC_FORM;
     g.Af = form(d.Hu + l * M2, d.Su + l * M2, M_, true, false, E_, eta_);
@@ -300,17 +300,17 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
       g.Cf.sub = mref(sigR_, Mp, MM_);
       g.Cf.sub_sign = -1.0;
     }
-    g.C = mref(Taug_, 2 * Mp, bs);
+    g.C = mref(T_, Mp, MM_);
     g.alpha = -1.0;
-    gemm(g, sweep_prec, true);
+    gemm(g, sp, true);
   }
   // G_1N = -W B^-1  (B^-1 when N = 1)
-  f = fill_args(mref(Taug_ + Mp, 2 * Mp, bs), Mp, Mp, FILL_IDENTITY);
-  f.flags = flags_;
-  f.flags_bs = Mp;
-  f.flags_n = Mp;
+  lu_factor(lu_, T_, MM_, Mp, B_, nullptr, N + 1, sp, tile, st_);
+  f = fill_args(mref(Y_, Mp, MM_), Mp, Mp, FILL_IDENTITY);
+  f.ridx = lu_.perm;
+  f.ridx_bs = Mp;
   launch_fill(f, B_, st_);
-  gje_prec(Taug_, 2 * Mp, bs, nullptr, N + 1, sweep_prec);
+  lu_solve(lu_, T_, MM_, Mp, Y_, MM_, Mp, B_, nullptr, sp, tile, st_);
   if (N == 1) {
     FillArgs c = fill_args(mref(P_, Mp, MM_), Mp, Mp, FILL_MAT);
     c.src = X;
@@ -321,7 +321,7 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
     g.B = X;
     g.C = mref(P_, Mp, MM_);
     g.alpha = -1.0;
-    gemm(g, sweep_prec, false);
+    gemm(g, sp, false);
   }
   GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
   g.A = mref(gamL_, Mp, MM_);
@@ -351,7 +351,5 @@ void Engine::export_sigma(z64* sigma_ws, rgf_z* out) {
 void Engine::lead_info(int side_bit, int32_t* done, int32_t* info) {
   launch_sr_info(done, side_bit, sing_, info, B_, 0, st_);
 }
-
-void Engine::reset_flags() { RGF_HIP(hipMemsetAsync(flags_, 0, (size_t)B_ * Mp_, st_)); }
 
 }  // namespace rgf

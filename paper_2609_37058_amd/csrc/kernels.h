@@ -50,45 +50,43 @@ struct GemmArgs {
 // Returns the algorithmic flops launched.
 double launch_gemm(const GemmArgs& g, int prec, int tile, hipStream_t st, int role = 0);
 
-// ------------------------------------------------- Gauss-Jordan elimination
-constexpr int GJE_NB = 64;
-struct PanelArgs {
-  MatRef T;  // augmented [B | RHS]; Mp rows; ld = width W
+// ------------------------------------------- LU with partial pivoting
+constexpr int LU_NB = 64;
+struct LuPanelArgs {
+  MatRef T;  // Mp x Mp per batch, factored in place; ld >= Mp
   int Mp;
-  int W;
   int k0;
-  z64* scratch;
-  int64_t scratch_bs;  // Mp x 64 per batch
-  z64* mult;
-  int64_t mult_bs;  // Mp x 64 per batch: elimination multipliers
-  z64* prow;
-  int64_t prow_bs;  // 64 x W per batch (ld W): pivot rows right of the panel
+  z64* linv;  // per batch: Mp/64 blocks of 64 x 64 (inverse diagonal blocks of L)
+  z64* uinv;  // per batch: Mp/64 blocks of 64 x 64 (inverse diagonal blocks of U)
+  int64_t inv_bs;
   int32_t* perm;
   int64_t perm_bs;  // Mp per batch
   uint8_t* flags;
   int64_t flags_bs;  // Mp per batch
-  int32_t* sing;     // per batch: first singular event code (0 = none)
+  int32_t* cand;
+  int64_t cand_bs;  // Mp per batch: rows still candidates after the panel, ascending
+  int32_t* sing;    // per batch: first singular event code (0 = none)
   int32_t sing_code;
   BatchCtl ctl;
 };
-void launch_gje_panel(const PanelArgs& a, int batch, hipStream_t st);
+void launch_lu_panel(const LuPanelArgs& a, int batch, hipStream_t st);
 
-// Buffers of a batched Gauss-Jordan solve (per batch: P 64 x 3Mp, scratch Mp x 64,
-// mult Mp x 64, perm Mp, flags Mp; sing 1).
-struct GjeBufs {
-  z64* P;
-  z64* scr;
-  z64* mult;
+// Buffers of a batched LU (per batch: linv, uinv 64 x Mp each, perm, cand Mp, flags Mp, sing 1).
+struct LuBufs {
+  z64* linv;
+  z64* uinv;
   int32_t* perm;
+  int32_t* cand;
   uint8_t* flags;
   int32_t* sing;
 };
-// Solve on T = [B | RHS] (Mp x W per batch, batch stride bs, flags already zero):
-// afterwards row perm[c] of the RHS columns holds row c of B^-1 RHS.  The block
-// products of the elimination run in `prec`; pivoting and the pivot-block
-// inverses are always FP64.  `timed` marks the products for the profiler.
-void gje_solve(const GjeBufs& g, z64* T, int W, int64_t bs, int Mp, int batch, const int32_t* skip,
-               int32_t code, int prec, int tile, hipStream_t st);
+// Factor T (Mp x Mp per batch, batch stride bs) in place.  Block products
+// (trailing updates) run in `prec`; pivoting and diagonal blocks in FP64.
+void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int32_t* skip, int32_t code,
+               int prec, int tile, hipStream_t st);
+// Y <- U^-1 L^-1 Y in place (Y = P RHS already gathered; Mp x nrhs per batch, ld nrhs).
+void lu_solve(const LuBufs& g, z64* T, int64_t bs, int Mp, z64* Y, int64_t ybs, int nrhs, int batch,
+              const int32_t* skip, int prec, int tile, hipStream_t st);
 
 // ---------------------------------------------------------- elementwise
 enum { FILL_ZERO = 0, FILL_IDENTITY = 1, FILL_MAT = 2, FILL_FORM = 3 };
@@ -102,6 +100,8 @@ struct FillArgs {
   uint8_t* flags;  // optional: zeroed (Mp per batch) -- reset of pivot flags
   int64_t flags_bs;
   int flags_n;
+  const int32_t* ridx;  // optional row gather of FORM / IDENTITY sources: source row = ridx[r]
+  int64_t ridx_bs;
   BatchCtl ctl;
 };
 void launch_fill(const FillArgs& a, int batch, hipStream_t st);
@@ -115,9 +115,6 @@ struct SrUpdateArgs {
   MatRef C;      // 2Mp x 2Mp products [aXa aXb; bXa bXb]
   MatRef eps, epsL, epsR;
   MatRef AB;     // 2Mp x Mp: alpha over beta
-  MatRef Tsr;    // Mp x 3Mp: next [eps | alpha | beta]
-  uint8_t* flags;
-  int64_t flags_bs;
   double* partial;  // per batch: gridDim.x blocks x 2 sums of squares
   int nblk;
   BatchCtl ctl;

@@ -1,0 +1,143 @@
+// Driver of the batched blocked LU with partial pivoting and of the two
+// block triangular solves that follow it.
+//
+// Factorisation, per 64-column panel (one panel kernel, two block products):
+//   B[piv, rest]  = L11^-1 B[piv, rest]            U12, rows = 64, K = 64
+//   B[cand, rest] -= B[cand, K] B[piv, rest]       trailing update, K = 64
+// over the candidate rows only (their ascending list comes from the panel
+// kernel), so the trailing work shrinks as the factorisation proceeds.
+// Solves, left-looking by 64-row blocks, so each block of the result is
+// written once with the whole inner dimension in one product:
+//   forward  Y_k = L_kk^-1 (Y_k - L[k, <k] Y_<k)
+//   backward Y_k = U_kk^-1 (Y_k - U[k, >k] Y_>k)
+// with L[k, :] = B[perm[k-block], :] (multipliers) and U likewise.
+#include "common.h"
+#include "kernels.h"
+
+namespace rgf {
+
+namespace {
+GemmArgs base_args(int rows, int cols, int K, int batch, const int32_t* skip) {
+  GemmArgs g;
+  g.rows = rows;
+  g.cols = cols;
+  g.K = K;
+  g.batch = batch;
+  g.a_kind = SRC_MAT;
+  g.A = nomat();
+  g.Af = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
+  g.B = nomat();
+  g.c_kind = SRC_NONE;
+  g.Cin = nomat();
+  g.Cf = g.Af;
+  g.C = nomat();
+  g.alpha = 1.0;
+  g.ctl.skip = skip;
+  return g;
+}
+}  // namespace
+
+void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int32_t* skip, int32_t code,
+               int prec, int tile, hipStream_t st) {
+  const int64_t inv_bs = (int64_t)64 * Mp;
+  {  // every row starts as a pivot candidate
+    FillArgs f;
+    f.dst = nomat();
+    f.rows = 0;
+    f.cols = 0;
+    f.kind = FILL_ZERO;
+    f.scale = 0.0;
+    f.src = nomat();
+    f.f = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
+    f.flags = g.flags;
+    f.flags_bs = Mp;
+    f.flags_n = Mp;
+    f.ridx = nullptr;
+    f.ridx_bs = 0;
+    f.ctl.skip = skip;
+    launch_fill(f, batch, st);
+  }
+  for (int k0 = 0; k0 < Mp; k0 += LU_NB) {
+    LuPanelArgs pa;
+    pa.T = mat(T, bs, Mp);
+    pa.Mp = Mp;
+    pa.k0 = k0;
+    pa.linv = g.linv;
+    pa.uinv = g.uinv;
+    pa.inv_bs = inv_bs;
+    pa.perm = g.perm;
+    pa.perm_bs = Mp;
+    pa.flags = g.flags;
+    pa.flags_bs = Mp;
+    pa.cand = g.cand;
+    pa.cand_bs = Mp;
+    pa.sing = g.sing;
+    pa.sing_code = code;
+    pa.ctl.skip = skip;
+    launch_lu_panel(pa, batch, st);
+    const int rest = Mp - k0 - LU_NB;
+    if (rest <= 0) continue;
+    // U12 = L11^-1 B[piv, rest], in place (one row tile: each workgroup owns its columns)
+    GemmArgs u = base_args(LU_NB, rest, LU_NB, batch, skip);
+    u.A = mat(g.linv + (int64_t)(k0 / LU_NB) * 64 * 64, inv_bs, 64);
+    u.B = mat(T + k0 + LU_NB, bs, Mp, g.perm + k0, Mp);
+    u.C = u.B;
+    launch_gemm(u, prec, tile, st, 0);
+    // B[cand, rest] -= B[cand, K] U12
+    GemmArgs t = base_args(rest, rest, LU_NB, batch, skip);
+    t.A = mat(T + k0, bs, Mp, g.cand, Mp);
+    t.B = mat(T + k0 + LU_NB, bs, Mp, g.perm + k0, Mp);
+    t.c_kind = SRC_MAT;
+    t.Cin = mat(T + k0 + LU_NB, bs, Mp, g.cand, Mp);
+    t.C = t.Cin;
+    t.alpha = -1.0;
+    launch_gemm(t, prec, tile, st, 0);
+  }
+}
+
+void lu_solve(const LuBufs& g, z64* T, int64_t bs, int Mp, z64* Y, int64_t ybs, int nrhs, int batch,
+              const int32_t* skip, int prec, int tile, hipStream_t st) {
+  const int64_t inv_bs = (int64_t)64 * Mp;
+  const int nb = Mp / LU_NB;
+  for (int k = 0; k < nb; ++k) {
+    const int k0 = k * LU_NB;
+    z64* Yk = Y + (int64_t)k0 * nrhs;
+    if (k0 > 0) {
+      GemmArgs o = base_args(LU_NB, nrhs, k0, batch, skip);
+      o.A = mat(T, bs, Mp, g.perm + k0, Mp);
+      o.B = mat(Y, ybs, nrhs);
+      o.c_kind = SRC_MAT;
+      o.Cin = mat(Yk, ybs, nrhs);
+      o.C = o.Cin;
+      o.alpha = -1.0;
+      launch_gemm(o, prec, tile, st, 0);
+    }
+    GemmArgs d = base_args(LU_NB, nrhs, LU_NB, batch, skip);
+    d.A = mat(g.linv + (int64_t)k * 64 * 64, inv_bs, 64);
+    d.B = mat(Yk, ybs, nrhs);
+    d.C = d.B;
+    launch_gemm(d, prec, tile, st, 0);
+  }
+  for (int k = nb - 1; k >= 0; --k) {
+    const int k0 = k * LU_NB;
+    z64* Yk = Y + (int64_t)k0 * nrhs;
+    const int rest = Mp - k0 - LU_NB;
+    if (rest > 0) {
+      GemmArgs o = base_args(LU_NB, nrhs, rest, batch, skip);
+      o.A = mat(T + k0 + LU_NB, bs, Mp, g.perm + k0, Mp);
+      o.B = mat(Yk + (int64_t)LU_NB * nrhs, ybs, nrhs);
+      o.c_kind = SRC_MAT;
+      o.Cin = mat(Yk, ybs, nrhs);
+      o.C = o.Cin;
+      o.alpha = -1.0;
+      launch_gemm(o, prec, tile, st, 0);
+    }
+    GemmArgs d = base_args(LU_NB, nrhs, LU_NB, batch, skip);
+    d.A = mat(g.uinv + (int64_t)k * 64 * 64, inv_bs, 64);
+    d.B = mat(Yk, ybs, nrhs);
+    d.C = d.B;
+    launch_gemm(d, prec, tile, st, 0);
+  }
+}
+
+}  // namespace rgf

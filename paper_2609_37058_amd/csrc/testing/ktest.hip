@@ -46,35 +46,44 @@ int rgf_ktest_gemm(int prec, int tile, int rows, int cols, int K, int batch, con
   });
 }
 
-// X[b] = B[b]^-1 RHS[b] by the batched Gauss-Jordan solve; T[b] = [B | RHS] (Mp x W) is destroyed.
-// perm/sing outputs are copied to the caller (perm: Mp ints per batch; sing: 1 int per batch).
-int rgf_ktest_gje(int prec, int Mp, int W, int batch, void* T, void* X, int32_t* perm_out, int32_t* sing_out) {
+// X[b] = B[b]^-1 RHS[b] by the batched LU and the two triangular solves; B (Mp x Mp) is destroyed,
+// RHS (Mp x nrhs, host order) is read; X (Mp x nrhs) receives the solution.
+int rgf_ktest_lu(int prec, int Mp, int nrhs, int batch, void* B, const void* RHS, void* X, int32_t* perm_out,
+                 int32_t* sing_out) {
   return kt_guard([&] {
-    GjeBufs g;
-    RGF_HIP(hipMalloc((void**)&g.P, sizeof(z64) * batch * 64 * 3 * Mp));
-    RGF_HIP(hipMalloc((void**)&g.scr, sizeof(z64) * batch * Mp * 64));
-    RGF_HIP(hipMalloc((void**)&g.mult, sizeof(z64) * batch * Mp * 64));
+    LuBufs g;
+    RGF_HIP(hipMalloc((void**)&g.linv, sizeof(z64) * batch * 64 * Mp));
+    RGF_HIP(hipMalloc((void**)&g.uinv, sizeof(z64) * batch * 64 * Mp));
     RGF_HIP(hipMalloc((void**)&g.perm, sizeof(int32_t) * batch * Mp));
+    RGF_HIP(hipMalloc((void**)&g.cand, sizeof(int32_t) * batch * Mp));
     RGF_HIP(hipMalloc((void**)&g.flags, batch * Mp));
     RGF_HIP(hipMalloc((void**)&g.sing, sizeof(int32_t) * batch));
-    RGF_HIP(hipMemset(g.flags, 0, batch * Mp));
     RGF_HIP(hipMemset(g.sing, 0, sizeof(int32_t) * batch));
-    gje_solve(g, (z64*)T, W, (int64_t)Mp * W, Mp, batch, nullptr, 1, prec, 64, nullptr);
+    const int64_t bs = (int64_t)Mp * Mp, ybs = (int64_t)Mp * nrhs;
+    lu_factor(g, (z64*)B, bs, Mp, batch, nullptr, 1, prec, 128, nullptr);
+    FillArgs f;
+    f.dst = mat((z64*)X, ybs, nrhs);
+    f.rows = Mp;
+    f.cols = nrhs;
+    f.kind = FILL_MAT;
+    f.scale = 1.0;
+    f.src = mat((z64*)RHS, ybs, nrhs, g.perm, Mp);
+    f.f = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
+    f.flags = nullptr;
+    f.flags_bs = 0;
+    f.flags_n = 0;
+    f.ridx = nullptr;
+    f.ridx_bs = 0;
+    f.ctl.skip = nullptr;
+    launch_fill(f, batch, nullptr);
+    lu_solve(g, (z64*)B, bs, Mp, (z64*)X, ybs, nrhs, batch, nullptr, prec, 128, nullptr);
     RGF_HIP(hipDeviceSynchronize());
-    const int nr = W - Mp;
-    std::vector<int32_t> perm((size_t)batch * Mp);
-    RGF_HIP(hipMemcpy(perm.data(), g.perm, sizeof(int32_t) * batch * Mp, hipMemcpyDeviceToHost));
-    for (int b = 0; b < batch; ++b)
-      for (int c = 0; c < Mp; ++c)
-        RGF_HIP(hipMemcpy((z64*)X + ((int64_t)b * Mp + c) * nr,
-                          (z64*)T + (int64_t)b * Mp * W + (int64_t)perm[(size_t)b * Mp + c] * W + Mp,
-                          sizeof(z64) * nr, hipMemcpyDeviceToDevice));
-    if (perm_out) memcpy(perm_out, perm.data(), sizeof(int32_t) * batch * Mp);
+    if (perm_out) RGF_HIP(hipMemcpy(perm_out, g.perm, sizeof(int32_t) * batch * Mp, hipMemcpyDeviceToHost));
     if (sing_out) RGF_HIP(hipMemcpy(sing_out, g.sing, sizeof(int32_t) * batch, hipMemcpyDeviceToHost));
-    RGF_HIP(hipFree(g.P));
-    RGF_HIP(hipFree(g.scr));
-    RGF_HIP(hipFree(g.mult));
+    RGF_HIP(hipFree(g.linv));
+    RGF_HIP(hipFree(g.uinv));
     RGF_HIP(hipFree(g.perm));
+    RGF_HIP(hipFree(g.cand));
     RGF_HIP(hipFree(g.flags));
     RGF_HIP(hipFree(g.sing));
   });
