@@ -49,6 +49,9 @@ class Engine {
 
   z64* sigL() { return sigL_; }
   z64* sigR() { return sigR_; }
+  // Sigma of batch entry b (Mp x Mp, padded), e.g. to fill it from a cache or copy it out
+  z64* sigma_slot(int b, bool left) { return (left ? sigL_ : sigR_) + (int64_t)b * MM_; }
+  int64_t block_elems() const { return MM_; }
   int32_t* done_l() { return done_l_; }
   int32_t* done_r() { return done_r_; }
 

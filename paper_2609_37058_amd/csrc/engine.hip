@@ -13,6 +13,12 @@
 //                  B_{l+1} = A_{l+1} - L_{l+1} X (- Sigma_R on the last layer)
 //                G_1N = -W B_{N-1}^-1
 //   trace        T = Re sum (Gamma_L G_1N) .* conj(G_1N Gamma_R)
+// Mixed precision (prec = FP32): the block products of the sweep, of the LU
+// trailing updates and of the triangular solves run on the FP32 matrix cores
+// with FP32 accumulation; pivot search, the diagonal-block inverses,
+// decimation, self-energies and the trace stay in FP64, and the one explicit
+// block inverse of the sweep, g = B_{N-1}^-1, gets one FP64 Newton-Schulz
+// correction g <- g + g (I - B g) before G_1N = -W g.
 // This is the first-row-propagator recursion of the recursive Green's
 // function method written with solves instead of explicit inverses: per
 // point-layer it costs an LU (8/3 M^3 real flops), two triangular solves
@@ -305,23 +311,49 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
     gemm(g, sp, true);
   }
   // G_1N = -W B^-1  (B^-1 when N = 1)
+  const bool refine = sp != PREC_F64;
+  if (refine) {  // keep B_{N-1} for the FP64 correction of its inverse
+    FillArgs c = fill_args(mref(Z2_, Mp, MM_), Mp, Mp, FILL_MAT);
+    c.src = mref(T_, Mp, MM_);
+    launch_fill(c, B_, st_);
+  }
   lu_factor(lu_, T_, MM_, Mp, B_, nullptr, N + 1, sp, tile, st_);
   f = fill_args(mref(Y_, Mp, MM_), Mp, Mp, FILL_IDENTITY);
   f.ridx = lu_.perm;
   f.ridx_bs = Mp;
   launch_fill(f, B_, st_);
   lu_solve(lu_, T_, MM_, Mp, Y_, MM_, Mp, B_, nullptr, sp, tile, st_);
+  MatRef ginv = X;
+  if (refine) {
+    // one Newton-Schulz step in FP64: g <- g + g (I - B g)
+    GemmArgs r = gemm_args(Mp, Mp, Mp, B_);
+    r.A = mref(Z2_, Mp, MM_);
+    r.B = X;
+    r.c_kind = SRC_FORM;
+    r.Cf = form(nullptr, nullptr, 0, false, true, E_, eta_);  // identity
+    r.C = mref(Z1_, Mp, MM_);
+    r.alpha = -1.0;
+    gemm(r, PREC_F64, false);
+    GemmArgs c = gemm_args(Mp, Mp, Mp, B_);
+    c.A = X;
+    c.B = mref(Z1_, Mp, MM_);
+    c.c_kind = SRC_MAT;
+    c.Cin = X;
+    c.C = mref(Z2_, Mp, MM_);
+    gemm(c, PREC_F64, false);
+    ginv = mref(Z2_, Mp, MM_);
+  }
   if (N == 1) {
     FillArgs c = fill_args(mref(P_, Mp, MM_), Mp, Mp, FILL_MAT);
-    c.src = X;
+    c.src = ginv;
     launch_fill(c, B_, st_);
   } else {
     GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
     g.A = mref(Wcur, Mp, MM_);
-    g.B = X;
+    g.B = ginv;
     g.C = mref(P_, Mp, MM_);
     g.alpha = -1.0;
-    gemm(g, sp, false);
+    gemm(g, PREC_F64, false);
   }
   GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
   g.A = mref(gamL_, Mp, MM_);

@@ -214,3 +214,77 @@ def set_tile(precision, tile: int):
 
 def version() -> str:
     return load().rgf_version().decode()
+
+
+class Server:
+    """Continuous-batching transmission server (transport_open/submit/poll/close).
+
+    submit() takes HOST numpy arrays (complex128 blocks, float64 energies); they
+    are copied before it returns.  poll() returns None while the request runs,
+    else (T, info, latency_s) as numpy arrays / float.
+    """
+
+    def __init__(self, hbm_budget_bytes: int = 0, lead_cache_bytes: int = 0, max_slots: int = 0):
+        lib = load()
+        self._lib = lib
+        opts = rgf_server_opts(int(hbm_budget_bytes), int(lead_cache_bytes), int(max_slots))
+        h = C.c_void_p()
+        _check(lib.transport_open(C.byref(opts), C.byref(h)))
+        self._h = h
+        self._n = {}
+
+    def submit(self, hd, hu, sd, su, left, right, E, eta: float, precision="fp64",
+               lead_key_L: int = 0, lead_key_R: int = 0) -> int:
+        """Blocks as numpy complex128 arrays (hd, sd: [N, M, M]; hu, su: [N-1, M, M]; left/right:
+        (H00, H01, S00, S01)); E float64 [nE].  Equal lead keys must mean identical lead blocks."""
+        import numpy as np
+        arrs = [np.ascontiguousarray(x, dtype=np.complex128) for x in (hd, hu, sd, su)]
+        la = [np.ascontiguousarray(x, dtype=np.complex128) for x in left]
+        ra = [np.ascontiguousarray(x, dtype=np.complex128) for x in right]
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        N, M = arrs[0].shape[0], arrs[0].shape[-1]
+        p = lambda a: a.ctypes.data if a.size else None
+        d = rgf_device(N, M, p(arrs[0]), p(arrs[1]), p(arrs[2]), p(arrs[3]),
+                       rgf_lead(M, *[p(a) for a in la]), rgf_lead(M, *[p(a) for a in ra]))
+        t = C.c_uint64()
+        _check(self._lib.transport_submit(self._h, C.byref(d), int(lead_key_L), int(lead_key_R), E.ctypes.data,
+                                          len(E), float(eta), PRECISION[precision], C.byref(t)))
+        self._n[t.value] = len(E)
+        return t.value
+
+    def poll(self, ticket: int):
+        import numpy as np
+        n = self._n[ticket]
+        T = np.empty(n, np.float64)
+        info = np.empty(n, np.int32)
+        lat = C.c_double()
+        rc = self._lib.transport_poll(self._h, C.c_uint64(ticket), T.ctypes.data, info.ctypes.data, C.byref(lat))
+        if rc == RGF_EAGAIN:
+            return None
+        self._n.pop(ticket, None)
+        _check(rc)
+        return T, info, lat.value
+
+    def wait(self, ticket: int, poll_s: float = 0.002):
+        import time
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            time.sleep(poll_s)
+
+    def stats(self) -> dict:
+        s = rgf_server_stats()
+        _check(self._lib.transport_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in rgf_server_stats._fields_}
+
+    def close(self):
+        if self._h:
+            _check(self._lib.transport_close(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

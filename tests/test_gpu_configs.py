@@ -1,0 +1,114 @@
+"""GPU parity at the full workload sizes, against stored oracle values.
+
+The expected values in tests/golden/<cfg>.json were written by
+tests/golden/make_golden.py, which calls only the FP64 oracle.  The GPU runs
+each workload in the configuration the benchmark times (whole energy batches,
+full layer count and block size) and the sampled energies are compared
+element by element.
+
+FP64 bar: |T_gpu - T_oracle| <= 1e-8 |T_oracle| + 1e-12.
+Mixed bar: |T_gpu - T_oracle| <= 1e-4.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import FP64_ATOL, FP64_RTOL, MIXED_ATOL, gpu_transmission, log, stage
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    path = os.path.join(GOLDEN, f"{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _compare(tag, T, g, precision):
+    ref = np.array(g["T"])
+    err = np.abs(T - ref)
+    if precision == "fp64":
+        ok = err <= FP64_RTOL * np.abs(ref) + FP64_ATOL
+    else:
+        ok = err <= MIXED_ATOL
+    log(f"[config] {tag} {precision}: max |dT| {err.max():.3e}, max rel {np.max(err / np.abs(ref)):.3e}, "
+        f"mean |dT| {err.mean():.3e}, T range [{ref.min():.3g}, {ref.max():.3g}]")
+    assert np.all(ok), list(zip(g["E"], T, ref))
+
+
+@pytest.fixture(scope="module")
+def c2_dev():
+    cfg = synth.config_c2()
+    return cfg, stage(cfg.device)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c2_all_energies(lib, c2_dev, precision):
+    """60 layers, M = 256: all 1000 energies in one call; the sampled ones checked."""
+    cfg, dt = c2_dev
+    g = golden("c2")
+    log(f"[config] c2 {precision}: N={cfg.device.N} M={cfg.device.M} nE={len(cfg.energies)}")
+    T, info = gpu_transmission(dt, cfg.energies, cfg.eta, precision)
+    assert np.all(info == 0)
+    _compare("c2", T[g["indices"]], g, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c3_sampled(lib, precision):
+    """200 layers, M = 512, 5% doped layers: the sampled energies inside a 64-energy batch."""
+    cfg = synth.config_c3()
+    g = golden("c3")
+    dt = stage(cfg.device)
+    idx = np.array(g["indices"])
+    batch = np.concatenate([cfg.energies[idx], cfg.energies[:64 - len(idx)]])
+    log(f"[config] c3 {precision}: N={cfg.device.N} M={cfg.device.M} batch={len(batch)}")
+    T, info = gpu_transmission(dt, batch, cfg.eta, precision)
+    assert np.all(info == 0)
+    _compare("c3", T[:len(idx)], g, precision)
+
+
+def test_c4_sampled(lib):
+    """400 layers, M = 1024 (25 GiB of blocks): the sampled energies inside a 64-energy batch."""
+    cfg = synth.config_c4()
+    g = golden("c4")
+    dt = stage(cfg.device)
+    idx = np.array(g["indices"])
+    batch = np.concatenate([cfg.energies[idx], cfg.energies[100:100 + 64 - len(idx)]])
+    log(f"[config] c4 fp64: N={cfg.device.N} M={cfg.device.M} batch={len(batch)}")
+    T, info = gpu_transmission(dt, batch, cfg.eta, "fp64")
+    assert np.all(info == 0)
+    _compare("c4", T[:len(idx)], g, "fp64")
+    del dt
+    import torch
+    torch.cuda.empty_cache()
+
+
+def test_batch_invariance_and_determinism(lib, c2_dev):
+    """A result does not depend on the batch it runs in, and reruns are bitwise equal."""
+    cfg, dt = c2_dev
+    E = cfg.energies[::37]
+    T_all, _ = gpu_transmission(dt, E, cfg.eta)
+    T_again, _ = gpu_transmission(dt, E, cfg.eta)
+    T_alone = np.array([gpu_transmission(dt, E[k:k + 1], cfg.eta)[0][0] for k in (0, 7, len(E) - 1)])
+    T_rev, _ = gpu_transmission(dt, E[::-1], cfg.eta)
+    assert np.array_equal(T_all, T_again)
+    assert np.array_equal(T_all[[0, 7, len(E) - 1]], T_alone)
+    assert np.array_equal(T_all, T_rev[::-1])
+
+
+def test_c1_pristine_integer_channels_on_gpu(lib):
+    """The GPU's T for the pristine C1 device equals the leads' channel count away from band edges."""
+    import oracle
+    cfg = synth.config_c1()
+    T, info = gpu_transmission(stage(cfg.device), cfg.energies, cfg.eta)
+    nch = oracle.channel_count(cfg.device.left, cfg.energies)
+    ext = oracle.band_extrema(cfg.device.left)
+    keep = np.array([np.min(np.abs(ext - e)) > 1e-2 for e in cfg.energies])
+    assert np.max(np.abs(T - nch)[keep]) <= 1e-3
