@@ -101,9 +101,11 @@ enum {
  * synchronises the stream before reading T.  Inputs must stay valid until
  * the stream reaches the end of the enqueued work.
  * precision: RGF_FP64 (all arithmetic in FP64) or RGF_MIXED (the block
- * products of the sweep and of the elimination updates in FP32 matrix
- * arithmetic with FP32 accumulation; decimation, pivot search, pivot-block
- * inverses and one Newton-Schulz correction per block inverse in FP64).
+ * products selected by rgf_set_mixed_parts -- by default those of the sweep,
+ * of the LU trailing updates and of the triangular solves -- on the FP32
+ * matrix cores with FP32 accumulation; decimation, self-energies, pivot
+ * search, the diagonal-block inverses and the trace in FP64, and the final
+ * block inverse of the sweep refined by one FP64 Newton-Schulz step).
  * Two calls on different streams of one device may run concurrently; two
  * calls on the same stream are serialised by the stream.
  * Equal left and right lead pointers share one decimation loop.
@@ -125,8 +127,8 @@ int lead_self_energy(const rgf_lead* lead, int side, const double* E, int64_t nE
  * the HOST inputs (device blocks, energies) into library staging before it
  * returns, so the caller may free them at once; the request is admitted to
  * the GPU when the HBM budget and a slot allow; requests in flight overlap on
- * the device.  Lead self-energies are cached on the device per
- * (lead key, side, E bit pattern, eta, precision) under lead_cache_bytes;
+ * the device.  Lead self-energies (always FP64) are cached on the device per
+ * (lead key, side, E bit pattern, eta) under lead_cache_bytes;
  * equal keys MUST mean identical lead blocks.  transport_poll copies T and
  * info to HOST buffers [nE] and the submit-to-completion latency in seconds;
  * it returns RGF_EAGAIN while the request is not finished, and RGF_ENOTICKET
@@ -171,9 +173,24 @@ int rgf_release_workspaces(void);
 int rgf_profile(int enable);
 int rgf_profile_read(int64_t* launches, double* total_ms, double* flops);
 
-/* Tile configuration of the FP64 and mixed block products (see rgf_tune). */
+/* Tile configuration of the FP64 and mixed block products: 128 (128x128 output
+ * tiles, 64-row tiles for 64-row products) or 64 (64x64 tiles).  Applies to later
+ * calls in the process. */
 int rgf_get_tile(int precision, int32_t* tile);
 int rgf_set_tile(int precision, int32_t tile);
+
+/* Which block products of the sweep run on the FP32 matrix cores when
+ * precision == RGF_MIXED (later calls in the process; default RGF_MIXED_ALL).
+ * Pivot search, the diagonal-block inverses, decimation, self-energies and the
+ * trace are FP64 in every case. */
+enum {
+  RGF_MIXED_SWEEP = 1, /* W <- -W X and B' = A - L X */
+  RGF_MIXED_LU = 2,    /* trailing updates of the block LU */
+  RGF_MIXED_SOLVE = 4, /* block triangular solves */
+  RGF_MIXED_ALL = 7
+};
+int rgf_set_mixed_parts(int parts);
+int rgf_get_mixed_parts(void);
 
 #ifdef __cplusplus
 }

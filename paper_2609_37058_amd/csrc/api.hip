@@ -72,6 +72,8 @@ void profile_launch_end(hipStream_t st, double flops) {
 // ------------------------------------------------------------- tile config
 static int g_tile[2] = {128, 128};
 int tile_for(int prec) { return g_tile[prec == PREC_F64 ? 0 : 1]; }
+static int g_mixed_parts = RGF_MIXED_ALL;
+int mixed_parts() { return g_mixed_parts; }
 
 // -------------------------------------------------------------- workspaces
 struct Workspace {
@@ -306,6 +308,15 @@ int rgf_profile_read(int64_t* launches, double* total_ms, double* flops) {
     g_prof.flops = 0.0;
   });
 }
+
+int rgf_set_mixed_parts(int parts) {
+  return guarded([&] {
+    RGF_CHECK((parts & ~RGF_MIXED_ALL) == 0, RGF_EINVAL, "unknown RGF_MIXED_* bits");
+    g_mixed_parts = parts;
+  });
+}
+
+int rgf_get_mixed_parts(void) { return g_mixed_parts; }
 
 int rgf_get_tile(int precision, int32_t* tile) {
   return guarded([&] {

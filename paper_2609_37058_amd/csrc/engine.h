@@ -19,6 +19,7 @@ void profile_launch_end(hipStream_t st, double flops);
 bool profiling();
 
 int tile_for(int prec);
+int mixed_parts();  // RGF_MIXED_* bits in effect for the mixed path
 
 // Device memory for `batch` energies at padded block size Mp.
 struct Layout {

@@ -256,7 +256,12 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
   const int Mp = Mp_;
   const int64_t M2 = (int64_t)M_ * M_;
   const int N = d.N;
-  const int sp = prec_;
+  // mixed precision: which block products run on the FP32 matrix cores
+  // (bit 0: sweep products, bit 1: LU trailing updates, bit 2: triangular solves)
+  const int mask = prec_ != PREC_F64 ? mixed_parts() : 0;
+  const int sp = (mask & 1) ? PREC_F32 : PREC_F64;
+  const int lp = (mask & 2) ? PREC_F32 : PREC_F64;
+  const int tp = (mask & 4) ? PREC_F32 : PREC_F64;
   const int tile = tile_for(sp);
   const MatRef X = mref(Y_, Mp, MM_);
 
@@ -275,13 +280,13 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
   z64* Wnxt = Wb_;
   for (int l = 0; l + 1 < N; ++l) {
     // X = B_l^-1 U_l
-    lu_factor(lu_, T_, MM_, Mp, B_, nullptr, l + 1, sp, tile, st_);
+    lu_factor(lu_, T_, MM_, Mp, B_, nullptr, l + 1, lp, tile, st_);
     f = fill_args(mref(Y_, Mp, MM_), Mp, Mp, FILL_FORM);
     f.f = form(d.Hu + l * M2, d.Su + l * M2, M_, false, false, E_, eta_);
     f.ridx = lu_.perm;
     f.ridx_bs = Mp;
     launch_fill(f, B_, st_);
-    lu_solve(lu_, T_, MM_, Mp, Y_, MM_, Mp, B_, nullptr, sp, tile, st_);
+    lu_solve(lu_, T_, MM_, Mp, Y_, MM_, Mp, B_, nullptr, tp, tile, st_);
     if (l == 0) {
       FillArgs c = fill_args(mref(Wcur, Mp, MM_), Mp, Mp, FILL_MAT);
       c.src = X;
@@ -311,18 +316,18 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
     gemm(g, sp, true);
   }
   // G_1N = -W B^-1  (B^-1 when N = 1)
-  const bool refine = sp != PREC_F64;
+  const bool refine = (lp | tp) != PREC_F64;
   if (refine) {  // keep B_{N-1} for the FP64 correction of its inverse
     FillArgs c = fill_args(mref(Z2_, Mp, MM_), Mp, Mp, FILL_MAT);
     c.src = mref(T_, Mp, MM_);
     launch_fill(c, B_, st_);
   }
-  lu_factor(lu_, T_, MM_, Mp, B_, nullptr, N + 1, sp, tile, st_);
+  lu_factor(lu_, T_, MM_, Mp, B_, nullptr, N + 1, lp, tile, st_);
   f = fill_args(mref(Y_, Mp, MM_), Mp, Mp, FILL_IDENTITY);
   f.ridx = lu_.perm;
   f.ridx_bs = Mp;
   launch_fill(f, B_, st_);
-  lu_solve(lu_, T_, MM_, Mp, Y_, MM_, Mp, B_, nullptr, sp, tile, st_);
+  lu_solve(lu_, T_, MM_, Mp, Y_, MM_, Mp, B_, nullptr, tp, tile, st_);
   MatRef ginv = X;
   if (refine) {
     // one Newton-Schulz step in FP64: g <- g + g (I - B g)

@@ -69,6 +69,8 @@ SIGNATURES = {
     "rgf_profile": (C.c_int, [C.c_int]),
     "rgf_profile_read": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rgf_get_tile": (C.c_int, [C.c_int, C.POINTER(C.c_int32)]),
+    "rgf_set_mixed_parts": (C.c_int, [C.c_int]),
+    "rgf_get_mixed_parts": (C.c_int, []),
     "rgf_set_tile": (C.c_int, [C.c_int, C.c_int32]),
 }
 
@@ -210,6 +212,18 @@ def get_tile(precision="fp64") -> int:
 
 def set_tile(precision, tile: int):
     _check(load().rgf_set_tile(PRECISION[precision], int(tile)))
+
+
+MIXED_SWEEP, MIXED_LU, MIXED_SOLVE, MIXED_ALL = 1, 2, 4, 7
+
+
+def set_mixed_parts(parts: int):
+    """Which block products run in FP32 on the matrix cores for precision="mixed" (bit mask)."""
+    _check(load().rgf_set_mixed_parts(int(parts)))
+
+
+def get_mixed_parts() -> int:
+    return int(load().rgf_get_mixed_parts())
 
 
 def version() -> str:
