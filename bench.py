@@ -32,12 +32,12 @@ METRIC = "RGF energy-point*layers/s at block 1024 (FP64 vs mixed); p50/p99 solve
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--energies-per-step", type=int, default=128)
     ap.add_argument("--layers", type=int, default=400, help="principal layers (400 = the full workload)")
     ap.add_argument("--block", type=int, default=1024, help="block size M (1024 = the full workload)")
-    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="block-product tile (64/128); 0 = library default")
