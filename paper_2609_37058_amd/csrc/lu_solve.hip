@@ -6,11 +6,13 @@
 //   B[cand, rest] -= B[cand, K] B[piv, rest]       trailing update, K = 64
 // over the candidate rows only (their ascending list comes from the panel
 // kernel), so the trailing work shrinks as the factorisation proceeds.
-// Solves, left-looking by 64-row blocks, so each block of the result is
+// Solves, left-looking by 128-row blocks, so each block of the result is
 // written once with the whole inner dimension in one product:
 //   forward  Y_k = L_kk^-1 (Y_k - L[k, <k] Y_<k)
 //   backward Y_k = U_kk^-1 (Y_k - U[k, >k] Y_>k)
-// with L[k, :] = B[perm[k-block], :] (multipliers) and U likewise.
+// with L[k, :] = B[perm[k-block], :] (multipliers) and U likewise; the
+// 128 x 128 diagonal triangle is applied as two 64-row inverse blocks and one
+// 64-row coupling product.
 #include "common.h"
 #include "kernels.h"
 
@@ -95,48 +97,71 @@ void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int
   }
 }
 
+// Y_rows = Y_rows - A_rows Y_src  (rows x nrhs, inner dimension K)
+static void update(GemmArgs base, z64* Yrows, int rows, const MatRef& A, z64* Ysrc, int K, int64_t ybs, int nrhs,
+                   int prec, int tile, hipStream_t st) {
+  if (K <= 0) return;
+  GemmArgs o = base;
+  o.rows = rows;
+  o.cols = nrhs;
+  o.K = K;
+  o.A = A;
+  o.B = mat(Ysrc, ybs, nrhs);
+  o.c_kind = SRC_MAT;
+  o.Cin = mat(Yrows, ybs, nrhs);
+  o.C = o.Cin;
+  o.alpha = -1.0;
+  launch_gemm(o, prec, tile, st, 0);
+}
+
+// Y_rows = D Y_rows in place (64 rows: one row tile, so each workgroup owns its columns)
+static void diag(GemmArgs base, z64* Yrows, const z64* D, int64_t inv_bs, int64_t ybs, int nrhs, int prec, int tile,
+                 hipStream_t st) {
+  GemmArgs d = base;
+  d.rows = LU_NB;
+  d.cols = nrhs;
+  d.K = LU_NB;
+  d.A = mat(const_cast<z64*>(D), inv_bs, 64);
+  d.B = mat(Yrows, ybs, nrhs);
+  d.C = d.B;
+  launch_gemm(d, prec, tile, st, 0);
+}
+
 void lu_solve(const LuBufs& g, z64* T, int64_t bs, int Mp, z64* Y, int64_t ybs, int nrhs, int batch,
               const int32_t* skip, int prec, int tile, hipStream_t st) {
+  // Blocks of two panels (128 rows): one product over the whole inner dimension on
+  // 128-row tiles, then the 2 x 2 block triangle with 64-row products.
   const int64_t inv_bs = (int64_t)64 * Mp;
-  const int nb = Mp / LU_NB;
-  for (int k = 0; k < nb; ++k) {
-    const int k0 = k * LU_NB;
-    z64* Yk = Y + (int64_t)k0 * nrhs;
-    if (k0 > 0) {
-      GemmArgs o = base_args(LU_NB, nrhs, k0, batch, skip);
-      o.A = mat(T, bs, Mp, g.perm + k0, Mp);
-      o.B = mat(Y, ybs, nrhs);
-      o.c_kind = SRC_MAT;
-      o.Cin = mat(Yk, ybs, nrhs);
-      o.C = o.Cin;
-      o.alpha = -1.0;
-      launch_gemm(o, prec, tile, st, 0);
+  const int np = Mp / LU_NB;
+  const GemmArgs base = base_args(LU_NB, nrhs, LU_NB, batch, skip);
+  auto Yr = [&](int panel) { return Y + (int64_t)panel * LU_NB * nrhs; };
+  auto Lrows = [&](int panel, int col0) { return mat(T + col0, bs, Mp, g.perm + panel * LU_NB, Mp); };
+  auto Linv = [&](int panel) { return g.linv + (int64_t)panel * 64 * 64; };
+  auto Uinv = [&](int panel) { return g.uinv + (int64_t)panel * 64 * 64; };
+  // forward: L Z = Y
+  for (int p = 0; p < np; p += 2) {
+    const int two = (p + 1 < np) ? 2 : 1;
+    const int r0 = p * LU_NB;
+    update(base, Yr(p), two * LU_NB, Lrows(p, 0), Y, r0, ybs, nrhs, prec, tile, st);
+    diag(base, Yr(p), Linv(p), inv_bs, ybs, nrhs, prec, tile, st);
+    if (two == 2) {
+      update(base, Yr(p + 1), LU_NB, Lrows(p + 1, r0), Yr(p), LU_NB, ybs, nrhs, prec, tile, st);
+      diag(base, Yr(p + 1), Linv(p + 1), inv_bs, ybs, nrhs, prec, tile, st);
     }
-    GemmArgs d = base_args(LU_NB, nrhs, LU_NB, batch, skip);
-    d.A = mat(g.linv + (int64_t)k * 64 * 64, inv_bs, 64);
-    d.B = mat(Yk, ybs, nrhs);
-    d.C = d.B;
-    launch_gemm(d, prec, tile, st, 0);
   }
-  for (int k = nb - 1; k >= 0; --k) {
-    const int k0 = k * LU_NB;
-    z64* Yk = Y + (int64_t)k0 * nrhs;
-    const int rest = Mp - k0 - LU_NB;
-    if (rest > 0) {
-      GemmArgs o = base_args(LU_NB, nrhs, rest, batch, skip);
-      o.A = mat(T + k0 + LU_NB, bs, Mp, g.perm + k0, Mp);
-      o.B = mat(Yk + (int64_t)LU_NB * nrhs, ybs, nrhs);
-      o.c_kind = SRC_MAT;
-      o.Cin = mat(Yk, ybs, nrhs);
-      o.C = o.Cin;
-      o.alpha = -1.0;
-      launch_gemm(o, prec, tile, st, 0);
+  // backward: U X = Z
+  int p = np - 1;
+  while (p >= 0) {
+    const int two = (p >= 1) ? 2 : 1;
+    const int q = p - two + 1;  // first panel of this block
+    const int rend = (p + 1) * LU_NB;
+    update(base, Yr(q), two * LU_NB, Lrows(q, rend), Yr(p + 1), Mp - rend, ybs, nrhs, prec, tile, st);
+    diag(base, Yr(p), Uinv(p), inv_bs, ybs, nrhs, prec, tile, st);
+    if (two == 2) {
+      update(base, Yr(q), LU_NB, Lrows(q, p * LU_NB), Yr(p), LU_NB, ybs, nrhs, prec, tile, st);
+      diag(base, Yr(q), Uinv(q), inv_bs, ybs, nrhs, prec, tile, st);
     }
-    GemmArgs d = base_args(LU_NB, nrhs, LU_NB, batch, skip);
-    d.A = mat(g.uinv + (int64_t)k * 64 * 64, inv_bs, 64);
-    d.B = mat(Yk, ybs, nrhs);
-    d.C = d.B;
-    launch_gemm(d, prec, tile, st, 0);
+    p -= two;
   }
 }
 
