@@ -41,7 +41,24 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="block-product tile (64/128); 0 = library default")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (read once, written once), three "
+                         "times, and exit: the reference kernel that scales the HBM byte counters")
     return ap.parse_args()
+
+
+def copy_probe(mib: int) -> int:
+    """A plain elementwise copy of known size, for calibrating FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.mul(x, 2.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
+    return 0
 
 
 def cpu_baseline(cfg, budget_s: float):
@@ -82,6 +99,8 @@ def cpu_baseline(cfg, budget_s: float):
 
 def main():
     args = parse()
+    if args.copy_probe_mib:
+        return copy_probe(args.copy_probe_mib)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (one process, one MI355X); --gpus {args.gpus} is not supported. "
               "The path shards over energies with no exchange during compute; see the design notes.",

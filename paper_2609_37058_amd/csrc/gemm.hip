@@ -18,9 +18,12 @@
 //
 // Work split: a BM x BN output tile per workgroup of WGM x WGN wavefronts,
 // each wavefront owning a (BM/WGM) x (BN/WGN) block of 16x16 MFMA tiles.
-// K advances 16 complex columns per LDS stage; the next stage's global
-// loads are issued before the current stage's MFMAs, so HBM/L2 latency
-// hides behind the (64-cycle) FP64 MFMAs.  Tiles are handed out so that
+// K advances 16 complex columns per LDS stage, with two LDS stages: the
+// next stage's global loads are issued before the current stage's MFMAs and
+// written to the other LDS stage after them, so one barrier per stage
+// suffices and HBM/L2 latency hides behind the (64-cycle) FP64 MFMAs.
+// Shapes are multiples of 64; a 128-wide tile that overhangs the matrix
+// leaves its outer wavefront blocks idle.  Tiles are handed out so that
 // each of the 8 XCDs works on a contiguous range of (batch, row-tile,
 // col-tile) ids: the operands of one batch entry stay in one XCD's L2.
 #include "common.h"
@@ -59,7 +62,11 @@ struct CT<float> {
   __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-template <typename R, int BM, int BN, int WGM, int WGN, int ROLE>
+// How the A operand is staged: a per-batch matrix, a formed block z S - H,
+// or the adjoint form z S^+ - H^+ (read transposed, so staged k-major).
+enum { AK_MAT = 0, AK_FORM = 1, AK_FORM_CT = 2 };
+
+template <typename R, int BM, int BN, int WGM, int WGN, int AK, int ROLE>
 __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   typedef typename CT<R>::c cR;
   typedef typename CT<R>::acc accT;
@@ -69,10 +76,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int t
   constexpr int EA = BM * BK / NT;  // staged A elements per thread
   constexpr int EB = BK * BN / NT;  // staged B elements per thread
   constexpr int LDA = BM + 1, LDB = BN + 1;
+  constexpr bool FORM = AK != AK_MAT;
   static_assert(EA >= 1 && EB >= 1 && BK % EA == 0 && BN % EB == 0 && BM % EA == 0, "tile split");
+  static_assert(64 % EA == 0 && 64 % EB == 0 && WTM % 16 == 0 && WTN % 16 == 0, "64-row groups");
 
-  __shared__ cR As[BK * LDA];
-  __shared__ cR Bs[BK * LDB];
+  // two LDS stages: the next stage is stored while the current one feeds the MFMAs
+  __shared__ cR As[2][BK * LDA];
+  __shared__ cR Bs[2][BK * LDB];
 
   // ---- tile id, XCD-aware ----
   const int64_t total = (int64_t)tiles_m * tiles_n * g.batch;
@@ -89,6 +99,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int t
   const int wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
   const int row0 = tm * BM, col0 = tn * BN;
+  // rows and columns are multiples of 64, so a partial tile drops whole wavefront blocks
+  const bool w_active = (row0 + wm * WTM < g.rows) && (col0 + wn * WTN < g.cols);
 
   accT accr[FM][FN], acci[FM][FN];
 #pragma unroll
@@ -99,108 +111,125 @@ __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int t
       acci[i][j] = accT{0, 0, 0, 0};
     }
 
-  // ---- A staging: row-major map (BK/EA threads per row) or k-major (conj_t forms) ----
-  const bool a_form = g.a_kind == SRC_FORM;
-  const bool a_ct = a_form && g.Af.conj_t;
-  int a_r, a_k;  // this thread's first element of the A tile
-  if (a_ct) {
-    a_k = tid / (BM / EA);
-    a_r = (tid % (BM / EA)) * EA;
-  } else {
-    a_r = tid / (BK / EA);
-    a_k = (tid % (BK / EA)) * EA;
-  }
+  // ---- A staging: row-major map (BK/EA threads per row); k-major for the adjoint form ----
+  const int a_r = (AK == AK_FORM_CT) ? (tid % (BM / EA)) * EA : tid / (BK / EA);
+  const int a_k = (AK == AK_FORM_CT) ? tid / (BM / EA) : (tid % (BK / EA)) * EA;
+  // the thread's A rows lie in one 64-row group: valid or not as a whole
+  const bool a_ok = row0 + a_r < g.rows;
   const z64* a_ptr = nullptr;  // MAT: element (a_r, a_k) at k0 = 0
   const z64 *a_s = nullptr, *a_h = nullptr;
   int a_M = 0;
   z64 zz = zmake(0.0, 0.0);
-  if (a_form) {
+  if constexpr (FORM) {
     a_M = g.Af.M;
     a_s = g.Af.S;
     a_h = g.Af.H;
     zz = zmake(g.Af.E[b], g.Af.eta);
   } else {
-    a_ptr = g.A.p + mat_off(g.A, b, row0 + a_r, a_k);
+    a_ptr = g.A.p + mat_off(g.A, b, a_ok ? row0 + a_r : 0, a_k);
   }
+  const bool a_pad = FORM && g.Af.pad_identity;
   // ---- B staging: k-major map ----
   const int b_k = tid / (BN / EB);
   const int b_c = (tid % (BN / EB)) * EB;
-  const z64* b_base = g.B.p + b * g.B.bstride + col0 + b_c;
+  const bool b_ok = col0 + b_c < g.cols;
+  const z64* b_base = g.B.p + b * g.B.bstride + (b_ok ? col0 + b_c : 0);
   const int32_t* b_ridx = g.B.rowidx ? g.B.rowidx + (int64_t)b * g.B.ridx_bstride : nullptr;
 
-  z64 ra[EA], rb[EB];
-  auto load = [&](int k0) {
-    if (!a_form) {
-#pragma unroll
-      for (int e = 0; e < EA; ++e) ra[e] = a_ptr[k0 + e];
-    } else if (a_ct) {
-      const int gk = k0 + a_k;
-#pragma unroll
-      for (int e = 0; e < EA; ++e) {
-        const int gr = row0 + a_r + e;
-        z64 v = zmake(0.0, 0.0);
-        if (gr < a_M && gk < a_M) {
-          const int64_t o = (int64_t)gk * a_M + gr;
-          v = zform(zz, zconj(a_s[o]), zconj(a_h[o]));
-        }
-        ra[e] = v;
-      }
-    } else {
-      const int gr = row0 + a_r;
-#pragma unroll
-      for (int e = 0; e < EA; ++e) {
-        const int gk = k0 + a_k + e;
-        z64 v = zmake(0.0, 0.0);
-        if (gr < a_M && gk < a_M) {
-          const int64_t o = (int64_t)gr * a_M + gk;
-          v = zform(zz, a_s[o], a_h[o]);
-        }
-        ra[e] = v;
-      }
-    }
-    const int kr = k0 + b_k;
-    const int64_t brow = b_ridx ? (int64_t)b_ridx[kr] : (int64_t)kr;
-    const z64* bp = b_base + brow * g.B.ld;
-#pragma unroll
-    for (int e = 0; e < EB; ++e) rb[e] = bp[e];
-  };
-  auto store = [&]() {
-    if (a_ct) {
-#pragma unroll
-      for (int e = 0; e < EA; ++e) As[a_k * LDA + a_r + e] = CT<R>::cvt(ra[e]);
-    } else {
-#pragma unroll
-      for (int e = 0; e < EA; ++e) As[(a_k + e) * LDA + a_r] = CT<R>::cvt(ra[e]);
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) Bs[b_k * LDB + b_c + e] = CT<R>::cvt(rb[e]);
-  };
+  // Staging registers.  Formed operands keep the raw S and H entries here and
+  // form z S - H when the stage is written to LDS, so no load waits on another.
+  z64 ra[EA], rh[FORM ? EA : 1], rb[EB];
+  int b_row = b_ridx ? b_ridx[b_k] : 0;  // gathered row of B for the stage being loaded
 
-  load(0);
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (k0 + BK < g.K) load(k0 + BK);
+#define RGF_GEMM_LOAD(k0)                                                          \
+  do {                                                                             \
+    if constexpr (AK == AK_MAT) {                                                  \
+      _Pragma("unroll") for (int e = 0; e < EA; ++e) ra[e] = a_ptr[(k0) + e];      \
+    } else if constexpr (AK == AK_FORM_CT) {                                       \
+      const int gk = (k0) + a_k;                                                   \
+      _Pragma("unroll") for (int e = 0; e < EA; ++e) {                             \
+        const int gr = row0 + a_r + e;                                             \
+        const int64_t o = (gr < a_M && gk < a_M) ? (int64_t)gk * a_M + gr : 0;     \
+        ra[e] = a_s[o];                                                            \
+        rh[e] = a_h[o];                                                            \
+      }                                                                            \
+    } else {                                                                       \
+      const int gr = row0 + a_r;                                                   \
+      _Pragma("unroll") for (int e = 0; e < EA; ++e) {                             \
+        const int gk = (k0) + a_k + e;                                             \
+        const int64_t o = (gr < a_M && gk < a_M) ? (int64_t)gr * a_M + gk : 0;     \
+        ra[e] = a_s[o];                                                            \
+        rh[e] = a_h[o];                                                            \
+      }                                                                            \
+    }                                                                              \
+    const int64_t brow_ = b_ridx ? (int64_t)b_row : (int64_t)((k0) + b_k);         \
+    const z64* bp_ = b_base + brow_ * g.B.ld;                                      \
+    _Pragma("unroll") for (int e = 0; e < EB; ++e) rb[e] = bp_[e];                 \
+    /* gathered B rows: the next stage's row index is fetched one stage ahead, */  \
+    /* so no load of a stage waits on an index load */                             \
+    if (b_ridx && (k0) + BK < g.K) b_row = b_ridx[(k0) + BK + b_k];                \
+  } while (0)
+
+#define RGF_GEMM_STORE(buf, k0)                                                              \
+  do {                                                                                       \
+    cR* as_ = As[buf];                                                                       \
+    cR* bs_ = Bs[buf];                                                                       \
+    _Pragma("unroll") for (int e = 0; e < EA; ++e) {                                         \
+      const int r_ = row0 + a_r + ((AK == AK_FORM_CT) ? e : 0);                              \
+      const int k_ = (k0) + a_k + ((AK == AK_FORM_CT) ? 0 : e);                              \
+      z64 v_ = ra[e];                                                                        \
+      if constexpr (AK == AK_FORM_CT) {                                                      \
+        v_ = (r_ < a_M && k_ < a_M) ? zform(zz, zconj(ra[e]), zconj(rh[e]))                  \
+                                    : zmake((a_pad && r_ == k_) ? 1.0 : 0.0, 0.0);           \
+      } else if constexpr (AK == AK_FORM) {                                                  \
+        v_ = (r_ < a_M && k_ < a_M) ? zform(zz, ra[e], rh[e])                                \
+                                    : zmake((a_pad && r_ == k_) ? 1.0 : 0.0, 0.0);           \
+      }                                                                                      \
+      if (!a_ok) v_ = zmake(0.0, 0.0);                                                       \
+      if constexpr (AK == AK_FORM_CT) as_[a_k * LDA + a_r + e] = CT<R>::cvt(v_);             \
+      else as_[(a_k + e) * LDA + a_r] = CT<R>::cvt(v_);                                      \
+    }                                                                                        \
+    _Pragma("unroll") for (int e = 0; e < EB; ++e)                                           \
+        bs_[b_k * LDB + b_c + e] = CT<R>::cvt(b_ok ? rb[e] : zmake(0.0, 0.0));               \
+  } while (0)
+
+  const int nst = g.K / BK;
+  RGF_GEMM_LOAD(0);
+  RGF_GEMM_STORE(0, 0);
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    const int cur = s & 1;
+    const bool more = s + 1 < nst;
+    if (more) RGF_GEMM_LOAD((s + 1) * BK);
+    if (w_active) {
+      const cR* as = As[cur];
+      const cR* bs = Bs[cur];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      cR af[FM], bf[FN];
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        cR af[FM], bf[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = As[kr * LDA + wm * WTM + i * 16 + (lane & 15)];
+        for (int i = 0; i < FM; ++i) af[i] = as[kr * LDA + wm * WTM + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = Bs[kr * LDB + wn * WTN + j * 16 + (lane & 15)];
+        for (int j = 0; j < FN; ++j) bf[j] = bs[kr * LDB + wn * WTN + j * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          accr[i][j] = CT<R>::mfma(af[i].x, bf[j].x, accr[i][j]);
-          accr[i][j] = CT<R>::mfma(-af[i].y, bf[j].y, accr[i][j]);
-          acci[i][j] = CT<R>::mfma(af[i].x, bf[j].y, acci[i][j]);
-          acci[i][j] = CT<R>::mfma(af[i].y, bf[j].x, acci[i][j]);
-        }
+          for (int j = 0; j < FN; ++j) {
+            accr[i][j] = CT<R>::mfma(af[i].x, bf[j].x, accr[i][j]);
+            accr[i][j] = CT<R>::mfma(-af[i].y, bf[j].y, accr[i][j]);
+            acci[i][j] = CT<R>::mfma(af[i].x, bf[j].y, acci[i][j]);
+            acci[i][j] = CT<R>::mfma(af[i].y, bf[j].x, acci[i][j]);
+          }
+      }
     }
+    // the other stage was last read before the previous barrier: safe to overwrite
+    if (more) RGF_GEMM_STORE(cur ^ 1, (s + 1) * BK);
+    __syncthreads();
   }
+#undef RGF_GEMM_LOAD
+#undef RGF_GEMM_STORE
+  if (!w_active) return;
 
   // ---- epilogue: C = Cin + alpha * acc ----
   const z64 zc = (g.c_kind == SRC_FORM) ? zmake(g.Cf.E[b], g.Cf.eta) : zmake(0.0, 0.0);
@@ -231,23 +260,38 @@ __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int t
       }
 }
 
-template <typename R, int BM, int BN, int WGM, int WGN>
-void launch_cfg(const GemmArgs& g, hipStream_t st, int role) {
-  const int tm = g.rows / BM, tn = g.cols / BN;
-  const int64_t total = (int64_t)tm * tn * g.batch;
+template <typename R, int BM, int BN, int WGM, int WGN, int AK>
+void launch_kind(const GemmArgs& g, dim3 grid, hipStream_t st, int role, int tm, int tn) {
   constexpr int NT = 64 * WGM * WGN;
   if (role == 1)
-    hipLaunchKernelGGL((zgemm_kernel<R, BM, BN, WGM, WGN, 1>), dim3((unsigned)total), dim3(NT), 0, st, g, tm, tn);
+    hipLaunchKernelGGL((zgemm_kernel<R, BM, BN, WGM, WGN, AK, 1>), grid, dim3(NT), 0, st, g, tm, tn);
   else
-    hipLaunchKernelGGL((zgemm_kernel<R, BM, BN, WGM, WGN, 0>), dim3((unsigned)total), dim3(NT), 0, st, g, tm, tn);
+    hipLaunchKernelGGL((zgemm_kernel<R, BM, BN, WGM, WGN, AK, 0>), grid, dim3(NT), 0, st, g, tm, tn);
 }
 
+template <typename R, int BM, int BN, int WGM, int WGN>
+void launch_cfg(const GemmArgs& g, hipStream_t st, int role) {
+  const int tm = (g.rows + BM - 1) / BM, tn = (g.cols + BN - 1) / BN;
+  // a product written in place over its B operand must keep each column block in one workgroup
+  const bool in_place = g.C.p == g.B.p && g.C.rowidx == g.B.rowidx && g.C.bstride == g.B.bstride;
+  RGF_CHECK(!(in_place && tm > 1), RGF_EINVAL, "gemm: in-place product spans several row tiles");
+  const dim3 grid((unsigned)((int64_t)tm * tn * g.batch));
+  if (g.a_kind != SRC_FORM)
+    launch_kind<R, BM, BN, WGM, WGN, AK_MAT>(g, grid, st, role, tm, tn);
+  else if (g.Af.conj_t)
+    launch_kind<R, BM, BN, WGM, WGN, AK_FORM_CT>(g, grid, st, role, tm, tn);
+  else
+    launch_kind<R, BM, BN, WGM, WGN, AK_FORM>(g, grid, st, role, tm, tn);
+}
+
+// Tile choice depends only on the shape and the requested tile size, never on
+// the batch, so a result does not depend on which other energies share a launch.
 template <typename R>
 void launch_prec(const GemmArgs& g, int tile, hipStream_t st, int role) {
-  if (tile >= 128 && g.rows % 128 == 0 && g.cols % 128 == 0) {
+  if (tile >= 128 && g.rows >= 128) {
     launch_cfg<R, 128, 128, 2, 4>(g, st, role);
-  } else if (tile >= 128 && g.cols % 128 == 0) {
-    launch_cfg<R, 64, 128, 1, 4>(g, st, role);
+  } else if (tile >= 128) {
+    launch_cfg<R, 64, 128, 2, 4>(g, st, role);
   } else {
     launch_cfg<R, 64, 64, 2, 2>(g, st, role);
   }
