@@ -6,6 +6,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "engine.h"
@@ -121,6 +122,37 @@ static int chunk_for(int Mp, int64_t nE) {
   return (int)b;
 }
 
+// ------------------------------------------------------------------- lanes
+// Internal streams (default priority) over which one call splits its energies.
+struct Lane {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, done = nullptr;
+};
+static std::mutex g_lane_mu;
+static std::map<int, std::vector<Lane>> g_lanes;
+
+static std::vector<Lane>& lane_streams(int dev, int n) {
+  std::lock_guard<std::mutex> lk(g_lane_mu);
+  std::vector<Lane>& v = g_lanes[dev];
+  while ((int)v.size() < n) {
+    Lane l;
+    RGF_HIP(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
+    RGF_HIP(hipEventCreateWithFlags(&l.fork, hipEventDisableTiming));
+    RGF_HIP(hipEventCreateWithFlags(&l.done, hipEventDisableTiming));
+    v.push_back(l);
+  }
+  return v;
+}
+
+// Lanes per call: two from padded block size 256 up (there the panel kernels,
+// one workgroup per energy, leave half the chip idle), else one.  RGF_LANES
+// overrides (1..4).
+static int lanes_for(int Mp) {
+  int n = Mp >= 256 ? 2 : 1;
+  if (const char* s = std::getenv("RGF_LANES")) n = std::atoi(s);
+  return std::max(1, std::min(n, 4));
+}
+
 // ----------------------------------------------------------- validation
 static void check_lead(const rgf_lead& l, int M, const char* name) {
   RGF_CHECK(l.H00 && l.H01 && l.S00 && l.S01, RGF_EINVAL, std::string(name) + ": null block pointer");
@@ -178,23 +210,57 @@ void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double 
   int dev = 0;
   RGF_HIP(hipGetDevice(&dev));
   const int prec = precision == RGF_MIXED ? PREC_F32 : PREC_F64;
-  for (int64_t e0 = 0; e0 < nE;) {
-    const int B = chunk_for(Mp, nE - e0);
-    const Layout lay = Layout::make(Mp, B);
-    Workspace& w = workspace(dev, st, lay.bytes);
-    Engine eng(w.base, lay, st, prec, M, E + e0, eta, w.host_active);
-    eng.decimate(d.left, eng.done_l());
-    eng.self_energy(d.left, true, eng.sigL());
-    int32_t* done_r = eng.done_l();
-    if (!same) {
-      eng.decimate(d.right, eng.done_r());
-      done_r = eng.done_r();
+  // energies [lo, hi) of one lane, in chunks of at most `chunk`, on stream `ls`
+  auto run_range = [&](int64_t lo, int64_t hi, int chunk, hipStream_t ls) {
+    for (int64_t e0 = lo; e0 < hi;) {
+      const int B = (int)std::min<int64_t>(chunk, hi - e0);
+      const Layout lay = Layout::make(Mp, B);
+      Workspace& w = workspace(dev, ls, lay.bytes);
+      Engine eng(w.base, lay, ls, prec, M, E + e0, eta, w.host_active);
+      eng.decimate(d.left, eng.done_l());
+      eng.self_energy(d.left, true, eng.sigL());
+      if (!same) eng.decimate(d.right, eng.done_r());
+      eng.self_energy(d.right, false, eng.sigR());
+      eng.broadenings();
+      eng.sweep_and_trace(d, T + e0, info ? info + e0 : nullptr, same);
+      e0 += B;
     }
-    (void)done_r;
-    eng.self_energy(d.right, false, eng.sigR());
-    eng.broadenings();
-    eng.sweep_and_trace(d, T + e0, info ? info + e0 : nullptr, same);
-    e0 += B;
+  };
+  const int chunk = chunk_for(Mp, nE);
+  const int nl = (int)std::min<int64_t>(lanes_for(Mp), nE);
+  if (nl <= 1) {
+    run_range(0, nE, chunk, st);
+    return;
+  }
+  // Several lanes: each takes a contiguous share of the energies on its own
+  // stream, driven by its own host thread, so one lane's latency-bound steps
+  // (pivot panels, decimation convergence checks) overlap the other lanes'
+  // matrix-core products.  Every per-energy step is independent of the
+  // other energies, so the results equal those of a single lane bitwise.
+  std::vector<Lane>& lanes = lane_streams(dev, nl);
+  RGF_HIP(hipEventRecord(lanes[0].fork, st));
+  std::vector<std::thread> th;
+  std::vector<Error> errs(nl, Error{RGF_OK, ""});
+  const int lane_chunk = std::max(1, chunk / nl);
+  for (int i = 0; i < nl; ++i) {
+    const int64_t lo = nE * i / nl, hi = nE * (i + 1) / nl;
+    th.emplace_back([&, i, lo, hi] {
+      try {
+        RGF_HIP(hipSetDevice(dev));
+        RGF_HIP(hipStreamWaitEvent(lanes[i].st, lanes[0].fork, 0));
+        run_range(lo, hi, lane_chunk, lanes[i].st);
+        RGF_HIP(hipEventRecord(lanes[i].done, lanes[i].st));
+      } catch (const Error& e) {
+        errs[i] = e;
+      } catch (const std::exception& e) {
+        errs[i] = Error{RGF_EDEVICE, e.what()};
+      }
+    });
+  }
+  for (auto& t : th) t.join();
+  for (int i = 0; i < nl; ++i) {
+    if (errs[i].code != RGF_OK) throw errs[i];
+    RGF_HIP(hipStreamWaitEvent(st, lanes[i].done, 0));
   }
 }
 

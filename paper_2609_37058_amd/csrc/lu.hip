@@ -5,21 +5,30 @@
 // perm[j] records the physical row that pivots column j.  In pivot order
 // the factors are
 //   L[j][m] = B[perm[j]][m]   (m < j, unit diagonal implied)
-//   U[j][c] = B[perm[j]][c]   (c >= j, outside the diagonal 64 x 64 blocks)
-// and the inverses of the diagonal blocks of L and U are kept per panel.
+//   U[j][c] = B[perm[j]][c]   (c >= j)
+// and the inverses of the diagonal 64 x 64 blocks of L and U are kept per
+// panel for the block products that follow.
 //
-// For the panel K = [k0, k0+64) this kernel
-//   1. factors the panel restricted to the rows not yet pivoted: per column
-//      the largest |Re|+|Im| wins (lowest row index on ties), found by a
-//      wavefront butterfly and a cross-wavefront pass in LDS; each
-//      candidate row r is eliminated in registers (8-column sub-panels,
-//      thread per row) and its multipliers l_r are written over its panel
-//      entries; the rest of the panel is updated in place (rank 8 from
-//      LDS-resident pivot rows);
-//   2. inverts the diagonal blocks L11 (unit lower, |l| <= 1) and U11 in LDS
-//      by Gauss-Jordan (no pivoting is needed for triangular blocks);
-//   3. writes perm, the flags and the ascending list of rows still
-//      candidates, which the trailing update of the matrix cores uses:
+// For the panel K = [k0, k0+64) one workgroup per batch entry (up to 512
+// threads; RPT = Mp / threads rows per thread) does:
+//   1. Sub-panels of SW columns, right-looking.  The thread keeps its row's
+//      SW sub-panel entries in registers.  Per column, each wavefront finds
+//      its largest |Re|+|Im| among the rows still candidates by a butterfly
+//      (lowest row index on ties) and the owner of that row publishes the
+//      row's sub-panel entries in an LDS slot; after ONE barrier every thread
+//      reduces the per-wavefront winners itself and reads the pivot row from
+//      the winner's slot, then eliminates in registers.  The two slot sets
+//      alternate between columns, so no second barrier is needed.
+//   2. After a sub-panel: candidates write their multipliers; the sub-panel's
+//      pivot rows at the remaining panel columns are formed by a forward
+//      substitution with their SW x SW unit-lower block (one thread per
+//      column); the candidates apply the rank-SW update to the rest of the
+//      panel, keeping the next sub-panel's entries in registers.
+//   3. The diagonal blocks are inverted by substitution, 16 lanes per column
+//      (each lane holds every 16th entry of the column; one 16-lane
+//      reduction per row), with no workgroup barrier.
+//   4. perm, the flags and the ascending list of rows still candidates are
+//      written; the matrix cores then form
 //        B[piv, rest]  = L11^-1 B[piv, rest]          (U12, in place)
 //        B[cand, rest] -= B[cand, K] B[piv, rest]     (l_r U12)
 #include "common.h"
@@ -30,31 +39,114 @@ namespace {
 
 constexpr int NB = LU_NB;
 constexpr int MAXMP = 2048;
+constexpr int MAXW = 8;  // wavefronts per workgroup (512 threads)
 
-// In-place Gauss-Jordan inverse of an NB x NB block in LDS, no pivoting.
-__device__ void lds_invert(z64* A, z64* colj, int tid, int nt) {
-  for (int j = 0; j < NB; ++j) {
-    const z64 inv = zinv(A[j * NB + j]);
-    __syncthreads();
-    if (tid < NB) {
-      const int c = tid;
-      A[j * NB + c] = (c == j) ? inv : zmul(A[j * NB + c], inv);
-      colj[c] = (c == j) ? zmake(0.0, 0.0) : A[c * NB + j];
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += nt) {
-      const int i = e / NB, c = e % NB;
-      if (i != j) {
-        const z64 base = (c == j) ? zmake(0.0, 0.0) : A[e];
-        A[e] = zfms(colj[i], A[j * NB + c], base);
+// ---- cross-lane steps on DPP row patterns (VALU latency, no LDS permute) ----
+// Within each row of 16 lanes: xor 1 and xor 2 (quad permutes), then the
+// half-row and row mirrors.  Applied in this order to a commutative
+// operation they leave every lane of the row with the same result.
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+
+template <int CTRL>
+__device__ inline int dpp32(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline uint64_t dpp64(uint64_t x) {
+  const int lo = dpp32<CTRL>((int)(uint32_t)x), hi = dpp32<CTRL>((int)(uint32_t)(x >> 32));
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+template <int CTRL>
+__device__ inline double dppd(double x) {
+  return __longlong_as_double((long long)dpp64<CTRL>((uint64_t)__double_as_longlong(x)));
+}
+template <int CTRL>
+__device__ inline z64 dppz(z64 v) { return zmake(dppd<CTRL>(v.x), dppd<CTRL>(v.y)); }
+
+__device__ inline uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+__device__ inline uint64_t readlane64(uint64_t x, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+// maximum over the 8 lanes of each half-row group, left in all of them
+__device__ inline uint64_t max8(uint64_t k) {
+  k = umax64(k, dpp64<DPP_XOR1>(k));
+  k = umax64(k, dpp64<DPP_XOR2>(k));
+  return umax64(k, dpp64<DPP_HALF_MIRROR>(k));
+}
+__device__ inline int min8(int r) {
+  r = min(r, dpp32<DPP_XOR1>(r));
+  r = min(r, dpp32<DPP_XOR2>(r));
+  return min(r, dpp32<DPP_HALF_MIRROR>(r));
+}
+// maximum over the whole wavefront (uniform result)
+__device__ inline uint64_t wave_max64(uint64_t k) {
+  k = max8(k);
+  k = umax64(k, dpp64<DPP_MIRROR>(k));
+  return umax64(umax64(readlane64(k, 0), readlane64(k, 16)), umax64(readlane64(k, 32), readlane64(k, 48)));
+}
+// sum over each row of 16 lanes, identical in all of them
+__device__ inline z64 row_sum16(z64 s) {
+  s = zadd(s, dppz<DPP_XOR1>(s));
+  s = zadd(s, dppz<DPP_XOR2>(s));
+  s = zadd(s, dppz<DPP_HALF_MIRROR>(s));
+  return zadd(s, dppz<DPP_MIRROR>(s));
+}
+// Pivot key: |Re|+|Im| >= 0 orders like its IEEE bit pattern; +1 keeps 0 for "no candidate".
+__device__ inline uint64_t pivot_key(z64 v) { return (uint64_t)__double_as_longlong(zabs1(v)) + 1ull; }
+
+// X = L^-1 (unit lower) or X = U^-1 (upper), NB x NB row-major in LDS, into the
+// row-major global block `out`.  Column c is solved by 16 lanes (lane q holds
+// x[m] for m = q (mod 16)); a row costs one 16-lane reduction.
+template <bool LOWER>
+__device__ void tri_invert(const z64* A, const z64* dinv, z64* out, int tid, int nt) {
+  const int lane = tid & 63;
+  const int q = lane & 15;
+  for (int c = tid >> 4; c < NB; c += nt >> 4) {
+    z64 x[NB / 16];
+#pragma unroll
+    for (int h = 0; h < NB / 16; ++h) x[h] = zmake(0.0, 0.0);
+    if (LOWER) {
+#pragma unroll
+      for (int h = 0; h < NB / 16; ++h)
+        if (q + 16 * h == c) x[h] = zmake(1.0, 0.0);
+      for (int i = c + 1; i < NB; ++i) {
+        z64 s = zmake(0.0, 0.0);
+#pragma unroll
+        for (int h = 0; h < NB / 16; ++h) {
+          const int m = q + 16 * h;
+          if (m >= c && m < i) s = zfma(A[i * NB + m], x[h], s);
+        }
+        s = row_sum16(s);
+#pragma unroll
+        for (int h = 0; h < NB / 16; ++h)
+          if (q + 16 * h == i) x[h] = zneg(s);
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < NB / 16; ++h)
+        if (q + 16 * h == c) x[h] = dinv[c];
+      for (int i = c - 1; i >= 0; --i) {
+        z64 s = zmake(0.0, 0.0);
+#pragma unroll
+        for (int h = 0; h < NB / 16; ++h) {
+          const int m = q + 16 * h;
+          if (m > i && m <= c) s = zfma(A[i * NB + m], x[h], s);
+        }
+        s = row_sum16(s);
+#pragma unroll
+        for (int h = 0; h < NB / 16; ++h)
+          if (q + 16 * h == i) x[h] = zneg(zmul(s, dinv[i]));
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < NB / 16; ++h) out[(q + 16 * h) * NB + c] = x[h];
   }
 }
 
 template <int RPT, int SW>
-__global__ __launch_bounds__(1024) void lu_panel_kernel(LuPanelArgs a) {
+__global__ __launch_bounds__(512) void lu_panel_kernel(LuPanelArgs a) {
   constexpr int NSUB = NB / SW;
   const int b = blockIdx.x;
   if (a.ctl.skip && a.ctl.skip[b]) return;
@@ -62,170 +154,190 @@ __global__ __launch_bounds__(1024) void lu_panel_kernel(LuPanelArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
   const int Mp = a.Mp, k0 = a.k0;
 
-  __shared__ z64 U[NB * NB];   // U11 rows, then U11^-1
-  __shared__ z64 Lf[NB * NB];  // L11, then L11^-1
-  __shared__ z64 Ls[SW * SW];
-  __shared__ z64 colj[NB];
+  __shared__ z64 U[NB * NB];   // U11 in pivot order (row j = pivot of column k0 + j)
+  __shared__ z64 Lw[NB * NB];  // L11 multipliers of the pivot rows (strictly lower part)
+  __shared__ z64 slot[2][MAXW][SW];
+  __shared__ uint64_t skey[2][MAXW];
+  __shared__ int sidx[2][MAXW];
+  __shared__ z64 dinv[NB];
   __shared__ uint8_t fl[MAXMP];  // 0 candidate, 1 earlier pivot, 2 pivot of this panel
   __shared__ int piv[NB];
-  __shared__ double rv[16];
-  __shared__ int ri[16];
-  __shared__ int wcount[16];
-  __shared__ int sh_p, sh_sing, sh_base;
+  __shared__ int wcount[MAXW];
+  __shared__ int sh_sing, sh_base;
 
   uint8_t* gflags = a.flags + (int64_t)b * a.flags_bs;
   for (int r = tid; r < Mp; r += nt) fl[r] = gflags[r] ? 1 : 0;
   if (tid == 0) sh_sing = 0;
   __syncthreads();
-
   z64* Tb = a.T.p + (int64_t)b * a.T.bstride;
   const int64_t ld = a.T.ld;
 
   bool cand[RPT];
+  z64 v[RPT][SW];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int r = tid + i * nt;
     cand[i] = (r < Mp) && (fl[r] == 0);
+    const int64_t ro = (int64_t)(cand[i] ? r : 0) * ld + k0;  // rows past Mp read nothing
+#pragma unroll
+    for (int t = 0; t < SW; ++t) v[i][t] = cand[i] ? Tb[ro + t] : zmake(0.0, 0.0);
   }
 
-  z64 v[RPT][SW];
   for (int s = 0; s < NSUB; ++s) {
     const int cb = SW * s;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int r = tid + i * nt;
-#pragma unroll
-      for (int j = 0; j < SW; ++j) v[i][j] = cand[i] ? Tb[(int64_t)r * ld + k0 + cb + j] : zmake(0.0, 0.0);
-    }
-#pragma unroll
     for (int j = 0; j < SW; ++j) {
-      double best = -1.0;
-      int bi = 0x7fffffff;
+      const int buf = j & 1;
+      // ---- wavefront argmax of |Re|+|Im| over the candidate rows (lowest row on ties) ----
+      uint64_t key = 0;
+      int bi_local = 0;  // which of the thread's rows holds its best key (lowest on ties)
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        if (cand[i]) {
-          const double x = zabs1(v[i][j]);
-          if (x > best) {
-            best = x;
-            bi = tid + i * nt;
-          }
+        const uint64_t k = cand[i] ? pivot_key(v[i][j]) : 0ull;
+        if (k > key) {
+          key = k;
+          bi_local = i;
         }
       }
+      const uint64_t wmax = wave_max64(key);
+      // rows tid + i*nt: every row of share i lies below every row of share i+1,
+      // and within a share lower lanes hold lower rows
+      int bi = 0x7fffffff;
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
+      for (int i = RPT - 1; i >= 0; --i) {
+        const unsigned long long m = __ballot(key == wmax && wmax != 0 && bi_local == i);
+        if (m) bi = (wave << 6) + (int)__builtin_ctzll(m) + i * nt;
+      }
+      // the owner of the wavefront's winner publishes its sub-panel row
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        if (cand[i] && tid + i * nt == bi) {
+#pragma unroll
+          for (int t = 0; t < SW; ++t) slot[buf][wave][t] = v[i][t];
         }
       }
       if (lane == 0) {
-        rv[wave] = best;
-        ri[wave] = bi;
+        skey[buf][wave] = wmax;
+        sidx[buf][wave] = bi;
       }
       __syncthreads();
+      // ---- every wavefront reduces the per-wavefront winners itself ----
+      const uint64_t wk = lane < nwaves ? skey[buf][lane] : 0ull;
+      const int wr = lane < nwaves ? sidx[buf][lane] : 0x7fffffff;
+      const uint64_t gk = readlane64(max8(wk), 0);
+      const int gi = __builtin_amdgcn_readfirstlane(min8((wk == gk && lane < 8) ? wr : 0x7fffffff));
+      const int gw = (gi % nt) >> 6;  // wavefront that owns the winning row
+      const double gb = __longlong_as_double((long long)(gk - 1ull));
+      const int p = (gi < Mp) ? gi : 0;  // a square system always has a candidate left
+      z64 u[SW];
+#pragma unroll
+      for (int t = 0; t < SW; ++t) u[t] = slot[buf][gw][t];
       if (tid == 0) {
-        double bb = rv[0];
-        int bx = ri[0];
-        for (int w = 1; w < nwaves; ++w) {
-          if (rv[w] > bb || (rv[w] == bb && ri[w] < bx)) {
-            bb = rv[w];
-            bx = ri[w];
-          }
-        }
-        if (!(bb > 0.0)) sh_sing = 1;
-        if (bx >= Mp) bx = 0;  // no candidate left: cannot happen for a square system
-        sh_p = bx;
-        piv[cb + j] = bx;
+        piv[cb + j] = p;
+        if (!(gb > 0.0)) sh_sing = 1;
       }
-      __syncthreads();
-      const int p = sh_p;
+      // ---- the pivot row leaves the candidates; its entries are U (t >= j) and L (t < j) ----
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        if (tid + i * nt == p) {
-#pragma unroll
-          for (int t = j; t < SW; ++t) U[(cb + j) * NB + cb + t] = v[i][t];
-#pragma unroll
-          for (int m = 0; m < j; ++m) {
-            Ls[j * SW + m] = v[i][m];
-            Tb[(int64_t)p * ld + k0 + cb + m] = v[i][m];
-          }
+        if (cand[i] && tid + i * nt == p) {
           cand[i] = false;
           fl[p] = 2;
+#pragma unroll
+          for (int t = 0; t < SW; ++t) {
+            Tb[(int64_t)p * ld + k0 + cb + t] = v[i][t];
+            if (t >= j) U[(cb + j) * NB + cb + t] = v[i][t];
+            else Lw[(cb + j) * NB + cb + t] = v[i][t];
+          }
         }
       }
-      __syncthreads();
-      const z64 inv = zinv(U[(cb + j) * NB + cb + j]);
+      // ---- elimination in registers ----
+      const z64 inv = zinv(u[j]);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         if (cand[i]) {
           const z64 l = zmul(v[i][j], inv);
           v[i][j] = l;
 #pragma unroll
-          for (int t = j + 1; t < SW; ++t) v[i][t] = zfms(l, U[(cb + j) * NB + cb + t], v[i][t]);
+          for (int t = j + 1; t < SW; ++t) v[i][t] = zfms(l, u[t], v[i][t]);
         }
       }
     }
-    // multipliers over the sub-panel's entries
+    // multipliers of this sub-panel
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       if (cand[i]) {
-        const int r = tid + i * nt;
+        const int64_t ro = (int64_t)(tid + i * nt) * ld + k0 + cb;
 #pragma unroll
-        for (int m = 0; m < SW; ++m) Tb[(int64_t)r * ld + k0 + cb + m] = v[i][m];
+        for (int m = 0; m < SW; ++m) Tb[ro + m] = v[i][m];
       }
     }
+    __syncthreads();  // Lw rows of this sub-panel's pivots and their Tb rows are complete
     if (s + 1 < NSUB) {
       const int c_begin = cb + SW;
       const int nrem = NB - c_begin;
-      // pivot rows of this sub-panel: their U entries at the remaining panel columns
+      // pivot rows of this sub-panel at the remaining panel columns:
+      // U[cb+j][c] = B[p_j][c] - sum_{m<j} L[cb+j][cb+m] U[cb+m][c]
       if (tid < nrem) {
         const int c = c_begin + tid;
+        z64 x[SW];
+#pragma unroll
+        for (int j = 0; j < SW; ++j) x[j] = Tb[(int64_t)piv[cb + j] * ld + k0 + c];
+#pragma unroll
         for (int j = 0; j < SW; ++j) {
-          z64 x = Tb[(int64_t)piv[cb + j] * ld + k0 + c];
-          for (int m = 0; m < j; ++m) x = zfms(Ls[j * SW + m], U[(cb + m) * NB + c], x);
-          U[(cb + j) * NB + c] = x;
+#pragma unroll
+          for (int m = 0; m < j; ++m) x[j] = zfms(Lw[(cb + j) * NB + cb + m], x[m], x[j]);
+          U[(cb + j) * NB + c] = x[j];
+          Tb[(int64_t)piv[cb + j] * ld + k0 + c] = x[j];
         }
       }
       __syncthreads();
-      // remaining candidate rows: rank-SW update of the rest of the panel, in place
+      // rank-SW update of the candidates' remaining panel entries; the next
+      // sub-panel's entries stay in registers, the later ones go back in place
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         if (cand[i]) {
           z64* row = Tb + (int64_t)(tid + i * nt) * ld + k0;
-          for (int c = c_begin; c < NB; c += 8) {
-            z64 x[8];
+          z64 l[SW];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) x[q] = row[c + q];
+          for (int m = 0; m < SW; ++m) l[m] = v[i][m];
+#pragma unroll
+          for (int q = 0; q < SW; ++q) v[i][q] = row[c_begin + q];
+#pragma unroll
+          for (int m = 0; m < SW; ++m)
+#pragma unroll
+            for (int q = 0; q < SW; ++q) v[i][q] = zfms(l[m], U[(cb + m) * NB + c_begin + q], v[i][q]);
+          for (int c = c_begin + SW; c < NB; c += SW) {
+            z64 x[SW];
+#pragma unroll
+            for (int q = 0; q < SW; ++q) x[q] = row[c + q];
 #pragma unroll
             for (int m = 0; m < SW; ++m)
 #pragma unroll
-              for (int q = 0; q < 8; ++q) x[q] = zfms(v[i][m], U[(cb + m) * NB + c + q], x[q]);
+              for (int q = 0; q < SW; ++q) x[q] = zfms(l[m], U[(cb + m) * NB + c + q], x[q]);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) row[c + q] = x[q];
+            for (int q = 0; q < SW; ++q) row[c + q] = x[q];
           }
         }
       }
     }
-    __syncthreads();
   }
 
-  // ---- diagonal blocks: L11 (unit lower) and U11, inverted in LDS ----
+  // ---- diagonal blocks: L11 (unit lower, strictly lower part from the pivot rows) and U11 ----
   for (int e = tid; e < NB * NB; e += nt) {
     const int j = e / NB, m = e % NB;
-    Lf[e] = (m < j) ? Tb[(int64_t)piv[j] * ld + k0 + m] : zmake(m == j ? 1.0 : 0.0, 0.0);
+    if (m < j) {
+      if (m / SW != j / SW) Lw[e] = Tb[(int64_t)piv[j] * ld + k0 + m];  // earlier sub-panels: from B
+    } else {
+      Lw[e] = zmake(m == j ? 1.0 : 0.0, 0.0);
+    }
     if (m < j) U[e] = zmake(0.0, 0.0);
   }
+  if (tid < NB) dinv[tid] = zinv(U[tid * NB + tid]);
   __syncthreads();
-  lds_invert(Lf, colj, tid, nt);
-  lds_invert(U, colj, tid, nt);
   z64* li = a.linv + (int64_t)b * a.inv_bs + (int64_t)(k0 / NB) * NB * NB;
   z64* ui = a.uinv + (int64_t)b * a.inv_bs + (int64_t)(k0 / NB) * NB * NB;
-  for (int e = tid; e < NB * NB; e += nt) {
-    li[e] = Lf[e];
-    ui[e] = U[e];
-  }
+  tri_invert<true>(Lw, dinv, li, tid, nt);
+  tri_invert<false>(U, dinv, ui, tid, nt);
   if (tid < NB) a.perm[(int64_t)b * a.perm_bs + k0 + tid] = piv[tid];
   for (int r = tid; r < Mp; r += nt) gflags[r] = fl[r] ? 1 : 0;
   if (tid == 0 && sh_sing && a.sing && a.sing[b] == 0) a.sing[b] = a.sing_code;
@@ -258,10 +370,14 @@ __global__ __launch_bounds__(1024) void lu_panel_kernel(LuPanelArgs a) {
 
 void launch_lu_panel(const LuPanelArgs& a, int batch, hipStream_t st) {
   RGF_CHECK(a.Mp % 64 == 0 && a.Mp <= MAXMP, RGF_EINVAL, "lu panel: Mp must be a multiple of 64, <= 2048");
-  if (a.Mp <= 1024) {
-    hipLaunchKernelGGL((lu_panel_kernel<1, 8>), dim3(batch), dim3(a.Mp), 0, st, a);
+  // whole wavefronts only: the butterflies and the per-wavefront slots assume full waves
+  auto threads = [&](int rpt) { return (unsigned)round_up((a.Mp + rpt - 1) / rpt, 64); };
+  if (a.Mp <= 512) {
+    hipLaunchKernelGGL((lu_panel_kernel<1, 8>), dim3(batch), dim3(threads(1)), 0, st, a);
+  } else if (a.Mp <= 1024) {
+    hipLaunchKernelGGL((lu_panel_kernel<2, 8>), dim3(batch), dim3(threads(2)), 0, st, a);
   } else {
-    hipLaunchKernelGGL((lu_panel_kernel<2, 8>), dim3(batch), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((lu_panel_kernel<4, 8>), dim3(batch), dim3(threads(4)), 0, st, a);
   }
   RGF_HIP(hipGetLastError());
 }

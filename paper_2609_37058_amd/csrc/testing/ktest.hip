@@ -89,4 +89,117 @@ int rgf_ktest_lu(int prec, int Mp, int nrhs, int batch, void* B, const void* RHS
   });
 }
 
+// Pseudo-random complex entries in [-1, 1) plus `diag` on the diagonal (timing inputs).
+__global__ void kt_fill_random(z64* p, int64_t n, int64_t ld, int64_t rows_per_batch, double diag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+  h ^= h >> 31;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 29;
+  const double a = (double)(h >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+  const double b = (double)((h * 0x94D049BB133111EBull) >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+  const int64_t r = (i / ld) % rows_per_batch, c = i % ld;
+  p[i] = zmake(a + (r == c ? diag : 0.0), b);
+}
+
+static void kt_random(z64* p, int64_t n, int64_t ld, int64_t rows, double diag) {
+  hipLaunchKernelGGL(kt_fill_random, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, nullptr, p, n, ld, rows, diag);
+  RGF_HIP(hipGetLastError());
+}
+
+// Average duration (ms, HIP events) of `reps` launches of one batched block product
+// C = C - A B on device buffers it allocates; inplace: C aliases B (rows must fit one tile).
+int rgf_ktest_gemm_time(int prec, int tile, int rows, int cols, int K, int batch, int inplace, int reps,
+                        double* ms) {
+  return kt_guard([&] {
+    z64 *A, *B, *Cm;
+    const int64_t na = (int64_t)batch * rows * K, nb = (int64_t)batch * K * cols, nc = (int64_t)batch * rows * cols;
+    RGF_HIP(hipMalloc((void**)&A, sizeof(z64) * na));
+    RGF_HIP(hipMalloc((void**)&B, sizeof(z64) * nb));
+    RGF_HIP(hipMalloc((void**)&Cm, sizeof(z64) * nc));
+    kt_random(A, na, K, rows, 0.0);
+    kt_random(B, nb, cols, K, 0.0);
+    kt_random(Cm, nc, cols, rows, 0.0);
+    GemmArgs g;
+    g.rows = rows;
+    g.cols = cols;
+    g.K = K;
+    g.batch = batch;
+    g.a_kind = SRC_MAT;
+    g.A = mat(A, (int64_t)rows * K, K);
+    g.Af = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
+    g.B = mat(B, (int64_t)K * cols, cols);
+    g.c_kind = inplace ? SRC_NONE : SRC_MAT;
+    g.Cin = inplace ? g.B : mat(Cm, (int64_t)rows * cols, cols);
+    g.Cf = g.Af;
+    g.C = g.Cin;
+    g.alpha = -1.0;
+    g.ctl.skip = nullptr;
+    hipEvent_t e0, e1;
+    RGF_HIP(hipEventCreate(&e0));
+    RGF_HIP(hipEventCreate(&e1));
+    launch_gemm(g, prec, tile, nullptr, 0);
+    RGF_HIP(hipEventRecord(e0, nullptr));
+    for (int r = 0; r < reps; ++r) launch_gemm(g, prec, tile, nullptr, 0);
+    RGF_HIP(hipEventRecord(e1, nullptr));
+    RGF_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    RGF_HIP(hipEventElapsedTime(&t, e0, e1));
+    *ms = t / reps;
+    RGF_HIP(hipEventDestroy(e0));
+    RGF_HIP(hipEventDestroy(e1));
+    RGF_HIP(hipFree(A));
+    RGF_HIP(hipFree(B));
+    RGF_HIP(hipFree(Cm));
+  });
+}
+
+// Average durations (ms) of the batched LU factorisation and of the two triangular
+// solves with nrhs right-hand sides, on a random diagonally weighted matrix.
+int rgf_ktest_lu_time(int prec, int Mp, int nrhs, int batch, int reps, double* ms_factor, double* ms_solve) {
+  return kt_guard([&] {
+    LuBufs g;
+    z64 *B0, *B, *Y;
+    const int64_t bs = (int64_t)Mp * Mp, ybs = (int64_t)Mp * nrhs;
+    RGF_HIP(hipMalloc((void**)&g.linv, sizeof(z64) * batch * 64 * Mp));
+    RGF_HIP(hipMalloc((void**)&g.uinv, sizeof(z64) * batch * 64 * Mp));
+    RGF_HIP(hipMalloc((void**)&g.perm, sizeof(int32_t) * batch * Mp));
+    RGF_HIP(hipMalloc((void**)&g.cand, sizeof(int32_t) * batch * Mp));
+    RGF_HIP(hipMalloc((void**)&g.flags, batch * Mp));
+    RGF_HIP(hipMalloc((void**)&g.sing, sizeof(int32_t) * batch));
+    RGF_HIP(hipMalloc((void**)&B0, sizeof(z64) * batch * bs));
+    RGF_HIP(hipMalloc((void**)&B, sizeof(z64) * batch * bs));
+    RGF_HIP(hipMalloc((void**)&Y, sizeof(z64) * batch * ybs));
+    RGF_HIP(hipMemset(g.sing, 0, sizeof(int32_t) * batch));
+    kt_random(B0, batch * bs, Mp, Mp, 4.0);
+    kt_random(Y, batch * ybs, nrhs, Mp, 0.0);
+    hipEvent_t e[3];
+    for (auto& x : e) RGF_HIP(hipEventCreate(&x));
+    double tf = 0.0, ts = 0.0;
+    for (int r = 0; r <= reps; ++r) {
+      RGF_HIP(hipMemcpy(B, B0, sizeof(z64) * batch * bs, hipMemcpyDeviceToDevice));
+      RGF_HIP(hipEventRecord(e[0], nullptr));
+      lu_factor(g, B, bs, Mp, batch, nullptr, 1, prec, 128, nullptr);
+      RGF_HIP(hipEventRecord(e[1], nullptr));
+      lu_solve(g, B, bs, Mp, Y, ybs, nrhs, batch, nullptr, prec, 128, nullptr);
+      RGF_HIP(hipEventRecord(e[2], nullptr));
+      RGF_HIP(hipEventSynchronize(e[2]));
+      float a = 0.f, b = 0.f;
+      RGF_HIP(hipEventElapsedTime(&a, e[0], e[1]));
+      RGF_HIP(hipEventElapsedTime(&b, e[1], e[2]));
+      if (r > 0) {
+        tf += a;
+        ts += b;
+      }
+    }
+    *ms_factor = tf / reps;
+    *ms_solve = ts / reps;
+    for (auto& x : e) RGF_HIP(hipEventDestroy(x));
+    for (void* q : {(void*)g.linv, (void*)g.uinv, (void*)g.perm, (void*)g.cand, (void*)g.flags, (void*)g.sing,
+                    (void*)B0, (void*)B, (void*)Y})
+      RGF_HIP(hipFree(q));
+  });
+}
+
 }  // extern "C"

@@ -57,7 +57,8 @@ def test_gemm_matches_numpy(kt, prec, tile, rows, cols, K, batch):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("Mp,nrhs,batch", [(64, 64, 2), (128, 128, 3), (192, 384, 2), (256, 256, 1), (512, 128, 2)])
+@pytest.mark.parametrize("Mp,nrhs,batch", [(64, 64, 2), (128, 128, 3), (192, 384, 2), (256, 256, 1), (512, 128, 2),
+                                           (576, 64, 2), (1024, 128, 2)])
 def test_lu_solve_matches_numpy_solve(kt, prec, Mp, nrhs, batch):
     import torch
     rng = np.random.default_rng(Mp + nrhs)
@@ -80,4 +81,5 @@ def test_lu_solve_matches_numpy_solve(kt, prec, Mp, nrhs, batch):
     log(f"[kernel] lu rel err {err:.2e}")
     assert all(sorted(p) == list(range(Mp)) for p in perm)
     assert np.all(sing == 0)
-    assert err < (1e-11 if prec == 0 else 1e-3)
+    # FP32 trailing updates and solves: the error grows with the order of these row-scaled random systems
+    assert err < (1e-11 if prec == 0 else 1e-3 * max(1.0, Mp / 512))
