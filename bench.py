@@ -97,6 +97,43 @@ def cpu_baseline(cfg, budget_s: float):
     }
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "zgemm_sweep_c4_fp64_traffic.txt")
+
+
+def source_digest() -> str:
+    """Digest of the block-product source the HBM counters were taken on."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2609_37058_amd", "csrc", "gemm.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the sweep block product, from the committed counter summary.
+
+    The summary records FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the sweep
+    product on this workload's shape and of a plain copy of known size; each
+    counter is scaled by the copy's bytes / counter ratio.  None when the summary
+    is absent or was taken on a different block-product source.
+    """
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    kv = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    try:
+        if kv["gemm.hip sha256[:16]"] != source_digest():
+            return None
+        fetch = float(kv["sweep product FETCH_SIZE KiB/launch"]) * 1024 * float(kv["FETCH_SIZE scale"])
+        write = float(kv["sweep product WRITE_SIZE KiB/launch"]) * 1024 * float(kv["WRITE_SIZE scale"])
+        per_energy = (fetch + write) / float(kv["energies per launch"])
+    except (KeyError, ValueError):
+        return None
+    return per_energy
+
+
 def main():
     args = parse()
     if args.copy_probe_mib:
@@ -178,6 +215,9 @@ def main():
     peak = FP64_MFMA_PEAK_TFLOPS if hp == "fp64" else FP32_MFMA_PEAK_TFLOPS
     achieved = (kr["flops"] / (kr["ms"] / 1e3) / 1e12) if kr["ms"] > 0 else None
     lat = np.array(head["lat"])
+    # HBM bytes per launch: the counter summary is per energy, a launch covers flops / (8 Mp^3) energies
+    d_mp = -(-d.M // 64) * 64
+    traffic_per_energy = measured_traffic() if hp == "fp64" else None
     out = {
         "metric": METRIC,
         "value": head["value"],
@@ -202,7 +242,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": (achieved / peak) if achieved else None,
-            "traffic": None,
+            "traffic": (traffic_per_energy * kr["flops"] / max(1, kr["launches"]) / (8.0 * d_mp ** 3)
+                        if traffic_per_energy is not None and kr["launches"] else None),
             "launches": kr["launches"],
             "avg_launch_ms": kr["ms"] / max(1, kr["launches"]),
         },

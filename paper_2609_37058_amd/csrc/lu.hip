@@ -10,27 +10,29 @@
 // panel for the block products that follow.
 //
 // For the panel K = [k0, k0+64) one workgroup per batch entry (up to 512
-// threads; RPT = Mp / threads rows per thread) does:
-//   1. Sub-panels of SW columns, right-looking.  The thread keeps its row's
-//      SW sub-panel entries in registers.  Per column, each wavefront finds
-//      its largest |Re|+|Im| among the rows still candidates by a butterfly
-//      (lowest row index on ties) and the owner of that row publishes the
-//      row's sub-panel entries in an LDS slot; after ONE barrier every thread
-//      reduces the per-wavefront winners itself and reads the pivot row from
-//      the winner's slot, then eliminates in registers.  The two slot sets
-//      alternate between columns, so no second barrier is needed.
-//   2. After a sub-panel: candidates write their multipliers; the sub-panel's
-//      pivot rows at the remaining panel columns are formed by a forward
-//      substitution with their SW x SW unit-lower block (one thread per
-//      column); the candidates apply the rank-SW update to the rest of the
-//      panel, keeping the next sub-panel's entries in registers.
-//   3. The diagonal blocks are inverted by substitution, 16 lanes per column
-//      (each lane holds every 16th entry of the column; one 16-lane
-//      reduction per row), with no workgroup barrier.
-//   4. perm, the flags and the ascending list of rows still candidates are
-//      written; the matrix cores then form
-//        B[piv, rest]  = L11^-1 B[piv, rest]          (U12, in place)
-//        B[cand, rest] -= B[cand, K] B[piv, rest]     (l_r U12)
+// threads; RPT = Mp / threads rows per thread) works in sub-panels of SW
+// columns.  Rows still candidates are updated left-looking: a thread brings
+// its row's SW sub-panel entries up to date from its own earlier multipliers
+// and the U rows of the earlier pivots (in LDS), so no candidate row is
+// written back until its multipliers are final.  Pivot rows are updated
+// right-looking: once a sub-panel's SW pivots are known, their U rows at all
+// remaining panel columns are formed at once (a product with the earlier U
+// rows, then a forward substitution with their SW x SW unit-lower block).
+//   Per column, each wavefront finds its largest |Re|+|Im| among its
+//   candidate rows with DPP row steps and readlane (lowest row index on
+//   ties); the owner of that row publishes the row's sub-panel entries in an
+//   LDS slot; after ONE barrier every wavefront reduces the per-wavefront
+//   winners itself, reads the pivot row from the winner's slot and eliminates
+//   in registers.  The two slot sets alternate between columns.
+// The diagonal blocks L11 and U11 are then inverted by substitution with 8
+// lanes per column (one 8-lane DPP sum per row), and perm, the flags and the
+// ascending list of rows still candidates are written.  The matrix cores then
+// form
+//   B[piv, rest]  = L11^-1 B[piv, rest]          (U12, in place)
+//   B[cand, rest] -= B[cand, K] B[piv, rest]     (l_r U12)
+// Only the multipliers of candidate rows and the U12 rows outside the panel
+// are read back from B; the diagonal 64 x 64 block is represented by the two
+// inverses.
 #include "common.h"
 #include "kernels.h"
 
@@ -86,62 +88,58 @@ __device__ inline uint64_t wave_max64(uint64_t k) {
   k = umax64(k, dpp64<DPP_MIRROR>(k));
   return umax64(umax64(readlane64(k, 0), readlane64(k, 16)), umax64(readlane64(k, 32), readlane64(k, 48)));
 }
-// sum over each row of 16 lanes, identical in all of them
-__device__ inline z64 row_sum16(z64 s) {
-  s = zadd(s, dppz<DPP_XOR1>(s));
-  s = zadd(s, dppz<DPP_XOR2>(s));
-  s = zadd(s, dppz<DPP_HALF_MIRROR>(s));
-  return zadd(s, dppz<DPP_MIRROR>(s));
-}
 // Pivot key: |Re|+|Im| >= 0 orders like its IEEE bit pattern; +1 keeps 0 for "no candidate".
 __device__ inline uint64_t pivot_key(z64 v) { return (uint64_t)__double_as_longlong(zabs1(v)) + 1ull; }
 
+// sum over each group of 8 lanes (half rows), identical in all of them
+__device__ inline z64 sum8(z64 s) {
+  s = zadd(s, dppz<DPP_XOR1>(s));
+  s = zadd(s, dppz<DPP_XOR2>(s));
+  return zadd(s, dppz<DPP_HALF_MIRROR>(s));
+}
+
 // X = L^-1 (unit lower) or X = U^-1 (upper), NB x NB row-major in LDS, into the
-// row-major global block `out`.  Column c is solved by 16 lanes (lane q holds
-// x[m] for m = q (mod 16)); a row costs one 16-lane reduction.
+// row-major global block `out`.  Column c is solved by 8 lanes (lane q holds
+// x[m] for m = q (mod 8)); a row costs one 8-lane sum, and the next row's
+// entries are read from LDS while the current one is reduced.
 template <bool LOWER>
 __device__ void tri_invert(const z64* A, const z64* dinv, z64* out, int tid, int nt) {
-  const int lane = tid & 63;
-  const int q = lane & 15;
-  for (int c = tid >> 4; c < NB; c += nt >> 4) {
-    z64 x[NB / 16];
+  constexpr int H = NB / 8;
+  const int q = tid & 7;
+  for (int c = tid >> 3; c < NB; c += nt >> 3) {
+    z64 x[H];
 #pragma unroll
-    for (int h = 0; h < NB / 16; ++h) x[h] = zmake(0.0, 0.0);
-    if (LOWER) {
+    for (int h = 0; h < H; ++h) x[h] = zmake(0.0, 0.0);
 #pragma unroll
-      for (int h = 0; h < NB / 16; ++h)
-        if (q + 16 * h == c) x[h] = zmake(1.0, 0.0);
-      for (int i = c + 1; i < NB; ++i) {
-        z64 s = zmake(0.0, 0.0);
+    for (int h = 0; h < H; ++h)
+      if (q + 8 * h == c) x[h] = LOWER ? zmake(1.0, 0.0) : dinv[c];
+    const int i0 = LOWER ? c + 1 : c - 1, step = LOWER ? 1 : -1;
+    const int n = LOWER ? NB - 1 - c : c;  // rows left to solve
+    z64 a[H];
+    if (n > 0) {
 #pragma unroll
-        for (int h = 0; h < NB / 16; ++h) {
-          const int m = q + 16 * h;
-          if (m >= c && m < i) s = zfma(A[i * NB + m], x[h], s);
-        }
-        s = row_sum16(s);
+      for (int h = 0; h < H; ++h) a[h] = A[i0 * NB + q + 8 * h];
+    }
+    for (int k = 0, i = i0; k < n; ++k, i += step) {
+      z64 s = zmake(0.0, 0.0);
 #pragma unroll
-        for (int h = 0; h < NB / 16; ++h)
-          if (q + 16 * h == i) x[h] = zneg(s);
+      for (int h = 0; h < H; ++h) {
+        const int m = q + 8 * h;
+        const bool in = LOWER ? (m >= c && m < i) : (m > i && m <= c);
+        if (in) s = zfma(a[h], x[h], s);
       }
-    } else {
+      if (k + 1 < n) {
 #pragma unroll
-      for (int h = 0; h < NB / 16; ++h)
-        if (q + 16 * h == c) x[h] = dinv[c];
-      for (int i = c - 1; i >= 0; --i) {
-        z64 s = zmake(0.0, 0.0);
-#pragma unroll
-        for (int h = 0; h < NB / 16; ++h) {
-          const int m = q + 16 * h;
-          if (m > i && m <= c) s = zfma(A[i * NB + m], x[h], s);
-        }
-        s = row_sum16(s);
-#pragma unroll
-        for (int h = 0; h < NB / 16; ++h)
-          if (q + 16 * h == i) x[h] = zneg(zmul(s, dinv[i]));
+        for (int h = 0; h < H; ++h) a[h] = A[(i + step) * NB + q + 8 * h];
       }
+      s = sum8(s);
+      const z64 xi = LOWER ? zneg(s) : zneg(zmul(s, dinv[i]));
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+        if (q + 8 * h == i) x[h] = xi;
     }
 #pragma unroll
-    for (int h = 0; h < NB / 16; ++h) out[(q + 16 * h) * NB + c] = x[h];
+    for (int h = 0; h < H; ++h) out[(q + 8 * h) * NB + c] = x[h];
   }
 }
 
@@ -154,8 +152,8 @@ __global__ __launch_bounds__(512) void lu_panel_kernel(LuPanelArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
   const int Mp = a.Mp, k0 = a.k0;
 
-  __shared__ z64 U[NB * NB];   // U11 in pivot order (row j = pivot of column k0 + j)
-  __shared__ z64 Lw[NB * NB];  // L11 multipliers of the pivot rows (strictly lower part)
+  __shared__ z64 U[NB * NB];   // U11 rows in pivot order (row j = pivot of column k0 + j), all panel columns
+  __shared__ z64 Lw[NB * NB];  // L11 rows in pivot order (strictly lower part)
   __shared__ z64 slot[2][MAXW][SW];
   __shared__ uint64_t skey[2][MAXW];
   __shared__ int sidx[2][MAXW];
@@ -173,27 +171,42 @@ __global__ __launch_bounds__(512) void lu_panel_kernel(LuPanelArgs a) {
   const int64_t ld = a.T.ld;
 
   bool cand[RPT];
-  z64 v[RPT][SW];
-#pragma unroll
+  z64 v[RPT * SW];  // the thread's rows' sub-panel entries, row-major
+#pragma clang loop unroll(full)
   for (int i = 0; i < RPT; ++i) {
     const int r = tid + i * nt;
     cand[i] = (r < Mp) && (fl[r] == 0);
-    const int64_t ro = (int64_t)(cand[i] ? r : 0) * ld + k0;  // rows past Mp read nothing
-#pragma unroll
-    for (int t = 0; t < SW; ++t) v[i][t] = cand[i] ? Tb[ro + t] : zmake(0.0, 0.0);
   }
 
   for (int s = 0; s < NSUB; ++s) {
     const int cb = SW * s;
-#pragma unroll
+    // ---- candidates: sub-panel entries brought up to date (left-looking) ----
+#pragma clang loop unroll(full)
+    for (int i = 0; i < RPT; ++i) {
+      if (cand[i]) {
+        const z64* row = Tb + (int64_t)(tid + i * nt) * ld + k0;
+#pragma clang loop unroll(full)
+        for (int t = 0; t < SW; ++t) v[i * SW + (t)] = row[cb + t];
+        for (int m0 = 0; m0 < cb; m0 += 8) {
+          z64 l[8];
+#pragma clang loop unroll(full)
+          for (int m = 0; m < 8; ++m) l[m] = row[m0 + m];
+#pragma clang loop unroll(full)
+          for (int m = 0; m < 8; ++m)
+#pragma clang loop unroll(full)
+            for (int t = 0; t < SW; ++t) v[i * SW + (t)] = zfms(l[m], U[(m0 + m) * NB + cb + t], v[i * SW + (t)]);
+        }
+      }
+    }
+#pragma clang loop unroll(full)
     for (int j = 0; j < SW; ++j) {
       const int buf = j & 1;
       // ---- wavefront argmax of |Re|+|Im| over the candidate rows (lowest row on ties) ----
       uint64_t key = 0;
       int bi_local = 0;  // which of the thread's rows holds its best key (lowest on ties)
-#pragma unroll
+#pragma clang loop unroll(full)
       for (int i = 0; i < RPT; ++i) {
-        const uint64_t k = cand[i] ? pivot_key(v[i][j]) : 0ull;
+        const uint64_t k = cand[i] ? pivot_key(v[i * SW + (j)]) : 0ull;
         if (k > key) {
           key = k;
           bi_local = i;
@@ -203,17 +216,17 @@ __global__ __launch_bounds__(512) void lu_panel_kernel(LuPanelArgs a) {
       // rows tid + i*nt: every row of share i lies below every row of share i+1,
       // and within a share lower lanes hold lower rows
       int bi = 0x7fffffff;
-#pragma unroll
+#pragma clang loop unroll(full)
       for (int i = RPT - 1; i >= 0; --i) {
         const unsigned long long m = __ballot(key == wmax && wmax != 0 && bi_local == i);
         if (m) bi = (wave << 6) + (int)__builtin_ctzll(m) + i * nt;
       }
       // the owner of the wavefront's winner publishes its sub-panel row
-#pragma unroll
+#pragma clang loop unroll(full)
       for (int i = 0; i < RPT; ++i) {
         if (cand[i] && tid + i * nt == bi) {
-#pragma unroll
-          for (int t = 0; t < SW; ++t) slot[buf][wave][t] = v[i][t];
+#pragma clang loop unroll(full)
+          for (int t = 0; t < SW; ++t) slot[buf][wave][t] = v[i * SW + (t)];
         }
       }
       if (lane == 0) {
@@ -226,111 +239,90 @@ __global__ __launch_bounds__(512) void lu_panel_kernel(LuPanelArgs a) {
       const int wr = lane < nwaves ? sidx[buf][lane] : 0x7fffffff;
       const uint64_t gk = readlane64(max8(wk), 0);
       const int gi = __builtin_amdgcn_readfirstlane(min8((wk == gk && lane < 8) ? wr : 0x7fffffff));
-      const int gw = (gi % nt) >> 6;  // wavefront that owns the winning row
+      // wavefront that owns the winning row: the lowest lane holding it (lane w = wavefront w)
+      const unsigned long long wmask = __ballot(lane < nwaves && wr == gi);
+      const int gw = wmask ? (int)__builtin_ctzll(wmask) : 0;
       const double gb = __longlong_as_double((long long)(gk - 1ull));
       const int p = (gi < Mp) ? gi : 0;  // a square system always has a candidate left
-      z64 u[SW];
-#pragma unroll
-      for (int t = 0; t < SW; ++t) u[t] = slot[buf][gw][t];
+      const z64* u = slot[buf][gw];  // the pivot row's sub-panel entries (LDS broadcast reads)
       if (tid == 0) {
         piv[cb + j] = p;
         if (!(gb > 0.0)) sh_sing = 1;
       }
       // ---- the pivot row leaves the candidates; its entries are U (t >= j) and L (t < j) ----
-#pragma unroll
+#pragma clang loop unroll(full)
       for (int i = 0; i < RPT; ++i) {
         if (cand[i] && tid + i * nt == p) {
           cand[i] = false;
           fl[p] = 2;
-#pragma unroll
+#pragma clang loop unroll(full)
           for (int t = 0; t < SW; ++t) {
-            Tb[(int64_t)p * ld + k0 + cb + t] = v[i][t];
-            if (t >= j) U[(cb + j) * NB + cb + t] = v[i][t];
-            else Lw[(cb + j) * NB + cb + t] = v[i][t];
+            if (t >= j) U[(cb + j) * NB + cb + t] = v[i * SW + (t)];
+            else Lw[(cb + j) * NB + cb + t] = v[i * SW + (t)];
           }
         }
       }
       // ---- elimination in registers ----
       const z64 inv = zinv(u[j]);
-#pragma unroll
+#pragma clang loop unroll(full)
       for (int i = 0; i < RPT; ++i) {
         if (cand[i]) {
-          const z64 l = zmul(v[i][j], inv);
-          v[i][j] = l;
-#pragma unroll
-          for (int t = j + 1; t < SW; ++t) v[i][t] = zfms(l, u[t], v[i][t]);
+          const z64 l = zmul(v[i * SW + (j)], inv);
+          v[i * SW + (j)] = l;
+#pragma clang loop unroll(full)
+          for (int t = j + 1; t < SW; ++t) v[i * SW + (t)] = zfms(l, u[t], v[i * SW + (t)]);
         }
       }
     }
     // multipliers of this sub-panel
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int i = 0; i < RPT; ++i) {
       if (cand[i]) {
         const int64_t ro = (int64_t)(tid + i * nt) * ld + k0 + cb;
-#pragma unroll
-        for (int m = 0; m < SW; ++m) Tb[ro + m] = v[i][m];
+#pragma clang loop unroll(full)
+        for (int m = 0; m < SW; ++m) Tb[ro + m] = v[i * SW + (m)];
       }
     }
-    __syncthreads();  // Lw rows of this sub-panel's pivots and their Tb rows are complete
-    if (s + 1 < NSUB) {
-      const int c_begin = cb + SW;
-      const int nrem = NB - c_begin;
-      // pivot rows of this sub-panel at the remaining panel columns:
-      // U[cb+j][c] = B[p_j][c] - sum_{m<j} L[cb+j][cb+m] U[cb+m][c]
+    __syncthreads();  // piv[] of this sub-panel, Lw/U entries of its pivots
+    // ---- this sub-panel's pivot rows: L entries of earlier sub-panels, then U rows ----
+    for (int e = tid; e < SW * cb; e += nt) {
+      const int j = e / cb, m = e % cb;
+      Lw[(cb + j) * NB + m] = Tb[(int64_t)piv[cb + j] * ld + k0 + m];
+    }
+    __syncthreads();
+    const int c_begin = cb + SW;
+    const int nrem = NB - c_begin;
+    if (nrem > 0) {
+      // U[cb+j][c] = B[p_j][c] - sum_{m<cb} L[cb+j][m] U[m][c] for c >= c_begin
+      for (int e = tid; e < SW * nrem; e += nt) {
+        const int j = e / nrem, c = c_begin + e % nrem;
+        z64 x = Tb[(int64_t)piv[cb + j] * ld + k0 + c];
+        for (int m = 0; m < cb; ++m) x = zfms(Lw[(cb + j) * NB + m], U[m * NB + c], x);
+        U[(cb + j) * NB + c] = x;
+      }
+      __syncthreads();
+      // ... then the forward substitution with the sub-panel's unit-lower block
       if (tid < nrem) {
         const int c = c_begin + tid;
         z64 x[SW];
-#pragma unroll
-        for (int j = 0; j < SW; ++j) x[j] = Tb[(int64_t)piv[cb + j] * ld + k0 + c];
-#pragma unroll
-        for (int j = 0; j < SW; ++j) {
-#pragma unroll
+#pragma clang loop unroll(full)
+        for (int j = 0; j < SW; ++j) x[j] = U[(cb + j) * NB + c];
+#pragma clang loop unroll(full)
+        for (int j = 1; j < SW; ++j) {
+#pragma clang loop unroll(full)
           for (int m = 0; m < j; ++m) x[j] = zfms(Lw[(cb + j) * NB + cb + m], x[m], x[j]);
           U[(cb + j) * NB + c] = x[j];
-          Tb[(int64_t)piv[cb + j] * ld + k0 + c] = x[j];
         }
       }
       __syncthreads();
-      // rank-SW update of the candidates' remaining panel entries; the next
-      // sub-panel's entries stay in registers, the later ones go back in place
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        if (cand[i]) {
-          z64* row = Tb + (int64_t)(tid + i * nt) * ld + k0;
-          z64 l[SW];
-#pragma unroll
-          for (int m = 0; m < SW; ++m) l[m] = v[i][m];
-#pragma unroll
-          for (int q = 0; q < SW; ++q) v[i][q] = row[c_begin + q];
-#pragma unroll
-          for (int m = 0; m < SW; ++m)
-#pragma unroll
-            for (int q = 0; q < SW; ++q) v[i][q] = zfms(l[m], U[(cb + m) * NB + c_begin + q], v[i][q]);
-          for (int c = c_begin + SW; c < NB; c += SW) {
-            z64 x[SW];
-#pragma unroll
-            for (int q = 0; q < SW; ++q) x[q] = row[c + q];
-#pragma unroll
-            for (int m = 0; m < SW; ++m)
-#pragma unroll
-              for (int q = 0; q < SW; ++q) x[q] = zfms(l[m], U[(cb + m) * NB + c + q], x[q]);
-#pragma unroll
-            for (int q = 0; q < SW; ++q) row[c + q] = x[q];
-          }
-        }
-      }
     }
   }
 
-  // ---- diagonal blocks: L11 (unit lower, strictly lower part from the pivot rows) and U11 ----
+  // ---- diagonal blocks: unit diagonal of L11, zero lower part of U11 ----
   for (int e = tid; e < NB * NB; e += nt) {
     const int j = e / NB, m = e % NB;
-    if (m < j) {
-      if (m / SW != j / SW) Lw[e] = Tb[(int64_t)piv[j] * ld + k0 + m];  // earlier sub-panels: from B
-    } else {
-      Lw[e] = zmake(m == j ? 1.0 : 0.0, 0.0);
-    }
-    if (m < j) U[e] = zmake(0.0, 0.0);
+    if (m >= j) Lw[e] = zmake(m == j ? 1.0 : 0.0, 0.0);
+    else U[e] = zmake(0.0, 0.0);
   }
   if (tid < NB) dinv[tid] = zinv(U[tid * NB + tid]);
   __syncthreads();
@@ -373,9 +365,9 @@ void launch_lu_panel(const LuPanelArgs& a, int batch, hipStream_t st) {
   // whole wavefronts only: the butterflies and the per-wavefront slots assume full waves
   auto threads = [&](int rpt) { return (unsigned)round_up((a.Mp + rpt - 1) / rpt, 64); };
   if (a.Mp <= 512) {
-    hipLaunchKernelGGL((lu_panel_kernel<1, 8>), dim3(batch), dim3(threads(1)), 0, st, a);
+    hipLaunchKernelGGL((lu_panel_kernel<1, 16>), dim3(batch), dim3(threads(1)), 0, st, a);
   } else if (a.Mp <= 1024) {
-    hipLaunchKernelGGL((lu_panel_kernel<2, 8>), dim3(batch), dim3(threads(2)), 0, st, a);
+    hipLaunchKernelGGL((lu_panel_kernel<2, 16>), dim3(batch), dim3(threads(2)), 0, st, a);
   } else {
     hipLaunchKernelGGL((lu_panel_kernel<4, 8>), dim3(batch), dim3(threads(4)), 0, st, a);
   }
