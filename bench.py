@@ -124,7 +124,7 @@ def measured_traffic():
                 k, v = line[2:].split(":", 1)
                 kv[k.strip()] = v.strip().strip("`")
     try:
-        if kv["gemm.hip sha256[:16]"] != source_digest():
+        if kv["gemm.hip sha256 prefix"] != source_digest():
             return None
         fetch = float(kv["sweep product FETCH_SIZE KiB/launch"]) * 1024 * float(kv["FETCH_SIZE scale"])
         write = float(kv["sweep product WRITE_SIZE KiB/launch"]) * 1024 * float(kv["WRITE_SIZE scale"])
