@@ -114,6 +114,76 @@ int rgf_transmission(const rgf_device* dev, const double* E, int64_t nE, double 
                      int precision, double* T, int32_t* info, void* stream);
 
 /*
+ * rgf_transmission_batch -- the batching form: many devices of uneven block
+ * size, length and energy count in one call.  devs[ndev] (host array of host
+ * structs); E[d], T[d] and info[d] are host arrays of DEVICE pointers to
+ * nE[d] energies, results and statuses of device d (info, or any info[d], may
+ * be NULL).  Devices that take the small-block path (M <= 16, RGF_FP64) share
+ * ONE persistent launch whose workgroups draw (device, energy) items from a
+ * work counter until the list is exhausted; the others run costliest first on
+ * two internal streams driven by their own host threads.  Every T[d][k] equals
+ * what rgf_transmission returns for device d alone (bitwise: no step depends on
+ * the other devices or energies).  Same pointer, stream and precision
+ * conventions as rgf_transmission; the call returns once the work is
+ * enqueued.  RGF_EINVAL for ndev < 0, a null array or any invalid device.
+ */
+int rgf_transmission_batch(const rgf_device* devs, int32_t ndev, const double* const* E, const int64_t* nE,
+                           double eta, int precision, double* const* T, int32_t* const* info, void* stream);
+
+/*
+ * rgf_transmission_bias -- T(E, V_b) at finite bias with the zero-bias
+ * Hamiltonian (paper: Method, the paragraph after eq. (1): H0 is supplied to
+ * the NEGF solver at finite bias, without self-consistent iterations).  The
+ * device blocks are used as given; the left / right electrode is rigidly
+ * shifted by u_left / u_right (eV): H00 -> H00 + u S00, H01 -> H01 + u S01,
+ * S unchanged, so its self-energy is the zero-bias one at E - u.  For a
+ * symmetric bias V_b: u_left = +V_b/2, u_right = -V_b/2.  u_left = u_right = 0
+ * is rgf_transmission.  Same pointers, stream, precision and info conventions
+ * as rgf_transmission; RGF_EINVAL also for non-finite shifts.
+ */
+int rgf_transmission_bias(const rgf_device* dev, const double* E, int64_t nE, double eta, double u_left,
+                          double u_right, int precision, double* T, int32_t* info, void* stream);
+
+/*
+ * rgf_landauer_current -- the current of eq. (1) (paper: Method),
+ *   I = (2e/h) * integral dE [f(E, mu_left) - f(E, mu_right)] T(E),
+ * on the caller's grid: E[nE] (eV, ascending) and T[nE] are DEVICE pointers,
+ * f is the Fermi-Dirac occupation at temperature kT (eV; kT = 0: the step,
+ * 1/2 at E = mu), the integral is the trapezoid rule, and with energies in eV
+ * the prefactor is G0 = 2e^2/h (spin-degenerate conductance quantum, exact SI
+ * constants), so I[0] (DEVICE pointer) receives amperes.  One workgroup sums
+ * in a fixed order, so the result does not depend on the launch.  nE < 2
+ * gives 0.  RGF_EINVAL for nE < 0, null pointers, non-finite mu or kT < 0.
+ * Stream-ordered.
+ */
+int rgf_landauer_current(const double* E, const double* T, int64_t nE, double mu_left, double mu_right,
+                         double kT, double* I, void* stream);
+
+/*
+ * rgf_transmission_kmesh -- transmission averaged over transverse k-points
+ * (paper: Method, the transverse k-point meshes of the transport runs;
+ * Results, the cost per energy and per transverse k-point).  images[nR]
+ * (host array, 1 <= nR <= 32) holds the real-space blocks of the transverse
+ * lattice images R[r] = (R[2r], R[2r+1]) (host int32): image r's Hd, Hu, Sd,
+ * Su and electrode blocks are DEVICE pointers as in rgf_transmission, all
+ * images of the same N and M; a null block pointer is a zero block.  At the
+ * fractional wavevector k = (kpts[2j], kpts[2j+1]) (host) every block is
+ *   X(k) = sum_r X(R_r) exp(2 pi i (k_1 R_r1 + k_2 R_r2)),
+ * the k-resolved transmission T_k(E) is computed from the X(k) device, and
+ *   T[e] = sum_j weights[j] T_kj(E[e])            (weights: host, as given).
+ * The caller keeps X(-R) = X(R)^+ for on-site blocks (Hermitian X(k)).
+ * Outputs (DEVICE pointers): T[nE]; Tk[nk][nE] (may be NULL); info[nk][nE]
+ * (may be NULL).  Electrodes whose blocks are pointer-equal in every image
+ * share one decimation.  The assembled devices of up to 64 k-points at a
+ * time (within 20% of free memory) run as one rgf_transmission_batch.
+ * Stream-ordered; RGF_EINVAL for nR outside [1, 32], nk < 1, images of
+ * different N or M, or no image with electrode blocks.
+ */
+int rgf_transmission_kmesh(const rgf_device* images, int32_t nR, const int32_t* R, const double* kpts,
+                           const double* weights, int32_t nk, const double* E, int64_t nE, double eta,
+                           int precision, double* T, double* Tk, int32_t* info, void* stream);
+
+/*
  * lead_self_energy -- Sigma of one lead for side RGF_LEFT (L g_L U) or
  * RGF_RIGHT (U g_R L), written to sigma[nE][M][M] (device pointer, row-major,
  * device-side block).  Same pointer, stream and info conventions as
@@ -178,6 +248,53 @@ int rgf_profile_read(int64_t* launches, double* total_ms, double* flops);
  * calls in the process. */
 int rgf_get_tile(int precision, int32_t* tile);
 int rgf_set_tile(int precision, int32_t tile);
+
+/*
+ * Tuning table (the batching form's per-size configuration).  For each padded
+ * block size class Mp = ceil(M/64)*64 and precision, the library keeps the
+ * block-product tile (64 or 128) and the number of energy lanes (internal
+ * streams, each driven by its own host thread, over which one call splits its
+ * energies).  0 means the built-in default (tile: the rgf_set_tile value;
+ * lanes: 2 from Mp = 256, else 1).  A setting depends only on (M, precision),
+ * never on the batch, so a result does not depend on which energies share a
+ * call.  rgf_get_tuning reports the values in effect (defaults resolved);
+ * rgf_set_tuning returns RGF_EINVAL for M outside [1, 2048], a tile other than
+ * 0/64/128 or lanes outside [0, 4].  Settings apply to later calls in the process.
+ */
+int rgf_get_tuning(int32_t M, int precision, int32_t* tile, int32_t* lanes);
+int rgf_set_tuning(int32_t M, int precision, int32_t tile, int32_t lanes);
+
+/*
+ * Captured sweeps.  rgf_set_graphs(1) makes later calls (rgf_transmission and
+ * rgf_transmission_batch) capture the sweep of each energy chunk -- the layer
+ * recursion's LU panels, triangular solves and block products, the final
+ * inverse and the trace -- into a HIP graph the first time a (device blocks,
+ * N, M, chunk size, precision, tile, workspace, stream) combination is seen,
+ * and replay the instantiated graph on later calls of that shape; the
+ * energies are staged into the workspace and the outputs copied out, so a
+ * replay serves any energies and output buffers.  Decimation stays eager.
+ * At most 32 graphs are kept (least recently used dropped); freeing or
+ * growing a workspace drops the graphs that point into it.  Off by default
+ * (or as RGF_GRAPHS=1 in the environment sets it); ignored while rgf_profile
+ * is on.  The device blocks must stay at the same addresses for a replay to
+ * be valid: keep graphs off when a device's block memory is freed and reused.
+ */
+int rgf_set_graphs(int enable);
+int rgf_get_graphs(void);
+
+/*
+ * rgf_autotune -- measure the four (tile, lanes) choices {64, 128} x {1, 2}
+ * for block size M and `precision` by timing the production sweep (layer
+ * recursion, final inverse, trace) on a synthetic three-layer device of
+ * `batch` energies (0: 64; reduced to fit 40% of free device memory), store
+ * the fastest in the tuning table and return it in *tile and *lanes (either
+ * may be NULL).  ms[4] (may be NULL) receives the mean time of one sweep for
+ * (64,1), (64,2), (128,1), (128,2), -1 for a choice not timed (lanes 2 with one
+ * energy).  Synchronous: it allocates and frees its own device buffers and
+ * synchronises the device, so run it while no other call is in flight.  On an
+ * error the entry for (M, precision) is reset to the defaults.
+ */
+int rgf_autotune(int32_t M, int precision, int32_t batch, int32_t* tile, int32_t* lanes, double* ms);
 
 /* Which block products of the sweep run on the FP32 matrix cores when
  * precision == RGF_MIXED (later calls in the process; default RGF_MIXED_ALL).

@@ -20,3 +20,17 @@ from .rgf_oracle import (  # noqa: F401
     band_extrema,
     dyson_residual,
 )
+from .bias import (  # noqa: F401
+    G0,
+    shifted_lead,
+    transmission_bias,
+    fermi,
+    landauer_current,
+    current,
+)
+from .kmesh import (  # noqa: F401
+    bloch_sum,
+    device_at_k,
+    transmission_kmesh,
+    monkhorst_pack,
+)

@@ -1,8 +1,10 @@
 // C ABI of librgf: argument checks, per-(device, stream) workspaces,
 // chunking of the energy batch to the free device memory, kernel timing.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -70,9 +72,19 @@ void profile_launch_end(hipStream_t st, double flops) {
   if (g_prof.recs.size() > 4096) g_prof.drain();
 }
 
-// ------------------------------------------------------------- tile config
-static int g_tile[2] = {128, 128};
-int tile_for(int prec) { return g_tile[prec == PREC_F64 ? 0 : 1]; }
+// ------------------------------------------------------------- tuning table
+// Per (precision, padded block size class Mp/64): block-product tile and energy
+// lanes; 0 = the built-in default.  Written by rgf_set_tuning / rgf_autotune,
+// read by every later call.  A choice depends only on (M, precision), never on
+// the batch, so results do not depend on which energies share a call.
+static std::atomic<int> g_tune_tile[2][MAX_M / 64 + 1];
+static std::atomic<int> g_tune_lanes[2][MAX_M / 64 + 1];
+static std::atomic<int> g_tile_default[2] = {128, 128};
+static int pidx(int prec) { return prec == PREC_F64 ? 0 : 1; }
+int tile_for(int prec, int Mp) {
+  const int t = g_tune_tile[pidx(prec)][std::min(Mp / 64, MAX_M / 64)].load();
+  return t ? t : g_tile_default[pidx(prec)].load();
+}
 static int g_mixed_parts = RGF_MIXED_ALL;
 int mixed_parts() { return g_mixed_parts; }
 
@@ -85,6 +97,8 @@ struct Workspace {
 static std::mutex g_ws_mu;
 static std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 
+static void drop_graphs_on(const void* base);
+
 static Workspace& workspace(int dev, hipStream_t st, size_t need) {
   std::lock_guard<std::mutex> lk(g_ws_mu);
   Workspace& w = g_ws[{dev, st}];
@@ -92,6 +106,7 @@ static Workspace& workspace(int dev, hipStream_t st, size_t need) {
   if (w.bytes < need) {
     if (w.base) {
       RGF_HIP(hipStreamSynchronize(st));
+      drop_graphs_on(w.base);
       RGF_HIP(hipFree(w.base));
       w.base = nullptr;
       w.bytes = 0;
@@ -107,13 +122,14 @@ static Workspace& workspace(int dev, hipStream_t st, size_t need) {
   return w;
 }
 
-// Largest energy chunk whose workspace fits the memory budget.
-static int chunk_for(int Mp, int64_t nE) {
+// Largest energy chunk whose workspace fits the memory budget (a `share` of it
+// when several workers allocate side by side).
+static int chunk_for(int Mp, int64_t nE, double share = 1.0) {
   size_t fr = 0, tot = 0;
   RGF_HIP(hipMemGetInfo(&fr, &tot));
   double frac = 0.80;
   if (const char* s = std::getenv("RGF_MEM_FRACTION")) frac = std::atof(s);
-  const size_t budget = (size_t)(frac * (double)fr);
+  const size_t budget = (size_t)(frac * share * (double)fr);
   const size_t per = Layout::make(Mp, 1).bytes;
   int64_t b = std::max<int64_t>(1, (int64_t)(budget / std::max<size_t>(per, 1)));
   if (const char* s = std::getenv("RGF_MAX_CHUNK")) b = std::min<int64_t>(b, std::max(1, std::atoi(s)));
@@ -129,11 +145,16 @@ struct Lane {
   hipEvent_t fork = nullptr, done = nullptr;
 };
 static std::mutex g_lane_mu;
-static std::map<int, std::vector<Lane>> g_lanes;
+static std::map<int, std::vector<Lane>> g_lanes, g_workers;
 
-static std::vector<Lane>& lane_streams(int dev, int n) {
+static std::mutex& lane_mutex(int dev) {
+  static std::mutex mus[64];
+  return mus[dev & 63];
+}
+
+static std::vector<Lane>& lane_streams(int dev, int n, bool workers = false) {
   std::lock_guard<std::mutex> lk(g_lane_mu);
-  std::vector<Lane>& v = g_lanes[dev];
+  std::vector<Lane>& v = (workers ? g_workers : g_lanes)[dev];
   while ((int)v.size() < n) {
     Lane l;
     RGF_HIP(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
@@ -144,11 +165,12 @@ static std::vector<Lane>& lane_streams(int dev, int n) {
   return v;
 }
 
-// Lanes per call: two from padded block size 256 up (there the panel kernels,
-// one workgroup per energy, leave half the chip idle), else one.  RGF_LANES
-// overrides (1..4).
-static int lanes_for(int Mp) {
-  int n = Mp >= 256 ? 2 : 1;
+// Lanes per call: from the tuning table, else two from padded block size 256
+// up (there the panel kernels, one workgroup per energy, leave half the chip
+// idle), else one.  RGF_LANES overrides (1..4).
+int lanes_for(int Mp, int prec) {
+  int n = g_tune_lanes[pidx(prec)][std::min(Mp / 64, MAX_M / 64)].load();
+  if (!n) n = Mp >= 256 ? 2 : 1;
   if (const char* s = std::getenv("RGF_LANES")) n = std::atoi(s);
   return std::max(1, std::min(n, 4));
 }
@@ -170,74 +192,245 @@ static bool same_lead(const rgf_lead& a, const rgf_lead& b) {
   return a.H00 == b.H00 && a.H01 == b.H01 && a.S00 == b.S00 && a.S01 == b.S01;
 }
 
-constexpr int MAX_M = 2048;
+void check_device(const rgf_device& d) {
+  RGF_CHECK(d.N >= 1, RGF_EINVAL, "N < 1");
+  RGF_CHECK(d.M >= 1 && d.M <= MAX_M, RGF_EINVAL, "M must be in [1, 2048]");
+  RGF_CHECK(d.Hd && d.Sd, RGF_EINVAL, "null device block pointer");
+  RGF_CHECK(d.N == 1 || (d.Hu && d.Su), RGF_EINVAL, "null coupling block pointer");
+  check_lead(d.left, d.M, "left lead");
+  check_lead(d.right, d.M, "right lead");
+}
 
-// One device, energies [0, nE): small-block fused kernel or the batched path.
-void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
-                       int32_t* info, hipStream_t st) {
-  const int M = d.M;
-  const bool same = same_lead(d.left, d.right);
+bool uses_small_path(int M, int precision) {
   int small_max = SMALL_MAX_M;
   if (const char* s = std::getenv("RGF_SMALL_MAX_M")) small_max = std::min(SMALL_MAX_M, std::atoi(s));
-  if (M <= small_max && precision == RGF_FP64) {
-    SmallArgs a;
-    a.N = d.N;
-    a.M = M;
-    a.Hd = reinterpret_cast<const z64*>(d.Hd);
-    a.Hu = reinterpret_cast<const z64*>(d.Hu);
-    a.Sd = reinterpret_cast<const z64*>(d.Sd);
-    a.Su = reinterpret_cast<const z64*>(d.Su);
-    a.LH00 = reinterpret_cast<const z64*>(d.left.H00);
-    a.LH01 = reinterpret_cast<const z64*>(d.left.H01);
-    a.LS00 = reinterpret_cast<const z64*>(d.left.S00);
-    a.LS01 = reinterpret_cast<const z64*>(d.left.S01);
-    a.RH00 = reinterpret_cast<const z64*>(d.right.H00);
-    a.RH01 = reinterpret_cast<const z64*>(d.right.H01);
-    a.RS00 = reinterpret_cast<const z64*>(d.right.S00);
-    a.RS01 = reinterpret_cast<const z64*>(d.right.S01);
-    a.same_leads = same ? 1 : 0;
-    a.E = E;
-    a.nE = nE;
-    a.eta = eta;
-    a.T = T;
-    a.info = info;
-    a.sr_tol = SR_TOL;
-    a.sr_maxit = SR_MAXIT;
+  return M <= small_max && precision == RGF_FP64;
+}
+
+SmallArgs small_args(const rgf_device& d, const double* E, int64_t nE, double eta, double* T, int32_t* info) {
+  SmallArgs a;
+  a.N = d.N;
+  a.M = d.M;
+  a.Hd = reinterpret_cast<const z64*>(d.Hd);
+  a.Hu = reinterpret_cast<const z64*>(d.Hu);
+  a.Sd = reinterpret_cast<const z64*>(d.Sd);
+  a.Su = reinterpret_cast<const z64*>(d.Su);
+  a.LH00 = reinterpret_cast<const z64*>(d.left.H00);
+  a.LH01 = reinterpret_cast<const z64*>(d.left.H01);
+  a.LS00 = reinterpret_cast<const z64*>(d.left.S00);
+  a.LS01 = reinterpret_cast<const z64*>(d.left.S01);
+  a.RH00 = reinterpret_cast<const z64*>(d.right.H00);
+  a.RH01 = reinterpret_cast<const z64*>(d.right.H01);
+  a.RS00 = reinterpret_cast<const z64*>(d.right.S00);
+  a.RS01 = reinterpret_cast<const z64*>(d.right.S01);
+  a.same_leads = same_lead(d.left, d.right) ? 1 : 0;
+  a.E = E;
+  a.nE = nE;
+  a.eta = eta;
+  a.T = T;
+  a.info = info;
+  a.sr_tol = SR_TOL;
+  a.sr_maxit = SR_MAXIT;
+  a.u_l = 0.0;
+  a.u_r = 0.0;
+  return a;
+}
+
+// ------------------------------------------------------ captured sweeps
+// With graphs on, the sweep of one energy chunk (every layer's LU panels,
+// solves and block products, the final inverse and the trace) is captured
+// once per (device, shape, precision, tile, workspace, stream) into a HIP
+// graph and replayed on later calls.  The energies are staged into the
+// workspace first and the sweep writes T and info into the workspace, so the
+// captured arguments stay valid for any energies and output buffers.  The
+// sweep records no memset, only kernels.  Decimation stays eager: its
+// iteration count depends on the data.
+struct GraphKey {
+  const void *Hd, *Hu, *Sd, *Su, *lH01, *lS01, *rH01, *rS01;
+  int N, M, B, prec, parts, tile;
+  const void* base;
+  hipStream_t st;
+  bool operator<(const GraphKey& o) const {
+    return std::memcmp(this, &o, sizeof(GraphKey)) < 0;
+  }
+};
+struct GraphEntry {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  uint64_t used = 0;
+};
+static std::mutex g_graph_mu;
+static std::map<GraphKey, GraphEntry> g_graphs;
+static uint64_t g_graph_clock = 0;
+static std::atomic<int> g_graphs_on{-1};  // -1: from RGF_GRAPHS (default off)
+static constexpr size_t MAX_GRAPHS = 32;
+
+static bool graphs_enabled() {
+  int v = g_graphs_on.load();
+  if (v < 0) {
+    const char* s = std::getenv("RGF_GRAPHS");
+    v = (s && std::atoi(s) != 0) ? 1 : 0;
+  }
+  return v != 0 && !profiling();
+}
+
+static void drop_graph(GraphEntry& e) {
+  if (e.ex) (void)hipGraphExecDestroy(e.ex);
+  if (e.g) (void)hipGraphDestroy(e.g);
+  e.ex = nullptr;
+  e.g = nullptr;
+}
+
+// Graphs that point into a workspace about to be freed.
+static void drop_graphs_on(const void* base) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+    if (it->first.base == base) {
+      drop_graph(it->second);
+      it = g_graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+// Replay (capturing on first use) the sweep of `eng` on stream `ls`.
+static void sweep_graph(Engine& eng, const rgf_device& d, bool same, int B, int prec, char* base,
+                        const Layout& lay, hipStream_t ls) {
+  GraphKey k;
+  std::memset(&k, 0, sizeof(k));
+  k.Hd = d.Hd;
+  k.Hu = d.Hu;
+  k.Sd = d.Sd;
+  k.Su = d.Su;
+  k.lH01 = d.left.H01;
+  k.lS01 = d.left.S01;
+  k.rH01 = d.right.H01;
+  k.rS01 = d.right.S01;
+  k.N = d.N;
+  k.M = d.M;
+  k.B = B;
+  k.prec = prec;
+  k.parts = mixed_parts();
+  k.tile = tile_for(prec, lay.Mp);
+  k.base = base;
+  k.st = ls;
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  auto it = g_graphs.find(k);
+  if (it == g_graphs.end()) {
+    if (g_graphs.size() >= MAX_GRAPHS) {  // evict the least recently used
+      auto lru = g_graphs.begin();
+      for (auto j = g_graphs.begin(); j != g_graphs.end(); ++j)
+        if (j->second.used < lru->second.used) lru = j;
+      RGF_HIP(hipStreamSynchronize(lru->first.st));
+      drop_graph(lru->second);
+      g_graphs.erase(lru);
+    }
+    GraphEntry e;
+    RGF_HIP(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
+    try {
+      eng.sweep_and_trace(d, reinterpret_cast<double*>(base + lay.tout), reinterpret_cast<int32_t*>(base + lay.iout),
+                          same);
+    } catch (...) {
+      hipGraph_t broken = nullptr;
+      (void)hipStreamEndCapture(ls, &broken);
+      if (broken) (void)hipGraphDestroy(broken);
+      throw;
+    }
+    RGF_HIP(hipStreamEndCapture(ls, &e.g));
+    RGF_HIP(hipGraphInstantiate(&e.ex, e.g, nullptr, nullptr, 0));
+    it = g_graphs.emplace(k, e).first;
+  }
+  it->second.used = ++g_graph_clock;
+  RGF_HIP(hipGraphLaunch(it->second.ex, ls));
+}
+
+// Energies [lo, hi) of one device on one stream, in chunks of at most `chunk`.
+static void run_range(const rgf_device& d, const double* E, int64_t lo, int64_t hi, double eta, int precision,
+                      double* T, int32_t* info, int chunk, hipStream_t ls, double u_l, double u_r) {
+  const int M = d.M;
+  const int Mp = (int)round_up(M, 64);
+  // one decimation serves both sides only for the same electrode at the same shift
+  const bool same = same_lead(d.left, d.right) && u_l == u_r;
+  const bool biased = u_l != 0.0 || u_r != 0.0;
+  const int prec = precision == RGF_MIXED ? PREC_F32 : PREC_F64;
+  const bool graphs = graphs_enabled();
+  int dev = 0;
+  RGF_HIP(hipGetDevice(&dev));
+  for (int64_t e0 = lo; e0 < hi;) {
+    const int B = (int)std::min<int64_t>(chunk, hi - e0);
+    const Layout lay = Layout::make(Mp, B);
+    Workspace& w = workspace(dev, ls, lay.bytes);
+    const double* Ec = E + e0;
+    if (graphs) {  // stage the energies at a stable address
+      double* Ew = reinterpret_cast<double*>(w.base + lay.energies);
+      RGF_HIP(hipMemcpyAsync(Ew, Ec, sizeof(double) * B, hipMemcpyDeviceToDevice, ls));
+      Ec = Ew;
+    }
+    Engine eng(w.base, lay, ls, prec, M, Ec, eta, w.host_active);
+    if (biased) {  // a rigidly shifted electrode is the unshifted one at E - u
+      double* El = reinterpret_cast<double*>(w.base + lay.elead);
+      double* Er = reinterpret_cast<double*>(w.base + lay.erlead);
+      launch_shift(El, Ec, B, u_l, ls);
+      launch_shift(Er, Ec, B, u_r, ls);
+      eng.set_lead_energies(El, Er);
+    }
+    eng.decimate(d.left, eng.done_l(), true);
+    eng.self_energy(d.left, true, eng.sigL());
+    if (!same) eng.decimate(d.right, eng.done_r(), false);
+    eng.self_energy(d.right, false, eng.sigR());
+    eng.broadenings();
+    if (graphs) {
+      sweep_graph(eng, d, same, B, prec, w.base, lay, ls);
+      RGF_HIP(hipMemcpyAsync(T + e0, w.base + lay.tout, sizeof(double) * B, hipMemcpyDeviceToDevice, ls));
+      if (info)
+        RGF_HIP(hipMemcpyAsync(info + e0, w.base + lay.iout, sizeof(int32_t) * B, hipMemcpyDeviceToDevice, ls));
+    } else {
+      eng.sweep_and_trace(d, T + e0, info ? info + e0 : nullptr, same);
+    }
+    e0 += B;
+  }
+}
+
+void run_device(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
+                int32_t* info, hipStream_t st, double mem_share, double u_l, double u_r) {
+  if (nE <= 0) return;
+  if (uses_small_path(d.M, precision)) {
+    SmallArgs a = small_args(d, E, nE, eta, T, info);
+    a.u_l = u_l;
+    a.u_r = u_r;
     launch_small(a, st);
     return;
   }
-  const int Mp = (int)round_up(M, 64);
-  int dev = 0;
-  RGF_HIP(hipGetDevice(&dev));
+  const int Mp = (int)round_up(d.M, 64);
+  run_range(d, E, 0, nE, eta, precision, T, info, chunk_for(Mp, nE, mem_share), st, u_l, u_r);
+}
+
+// One device, energies [0, nE): small-block fused kernel or the batched path,
+// the latter split over the energy lanes.
+void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
+                       int32_t* info, hipStream_t st, double u_l, double u_r) {
+  const int Mp = (int)round_up(d.M, 64);
   const int prec = precision == RGF_MIXED ? PREC_F32 : PREC_F64;
-  // energies [lo, hi) of one lane, in chunks of at most `chunk`, on stream `ls`
-  auto run_range = [&](int64_t lo, int64_t hi, int chunk, hipStream_t ls) {
-    for (int64_t e0 = lo; e0 < hi;) {
-      const int B = (int)std::min<int64_t>(chunk, hi - e0);
-      const Layout lay = Layout::make(Mp, B);
-      Workspace& w = workspace(dev, ls, lay.bytes);
-      Engine eng(w.base, lay, ls, prec, M, E + e0, eta, w.host_active);
-      eng.decimate(d.left, eng.done_l());
-      eng.self_energy(d.left, true, eng.sigL());
-      if (!same) eng.decimate(d.right, eng.done_r());
-      eng.self_energy(d.right, false, eng.sigR());
-      eng.broadenings();
-      eng.sweep_and_trace(d, T + e0, info ? info + e0 : nullptr, same);
-      e0 += B;
-    }
-  };
-  const int chunk = chunk_for(Mp, nE);
-  const int nl = (int)std::min<int64_t>(lanes_for(Mp), nE);
-  if (nl <= 1) {
-    run_range(0, nE, chunk, st);
+  const bool small = uses_small_path(d.M, precision);
+  const int nl = small ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(lanes_for(Mp, prec), nE));
+  // Captured sweeps always run on library streams (a capture cannot run on the
+  // caller's stream when that is the legacy default stream), so one lane then
+  // also goes through the lane path.
+  if (small || (nl == 1 && !graphs_enabled())) {
+    run_device(d, E, nE, eta, precision, T, info, st, 1.0, u_l, u_r);
     return;
   }
+  int dev = 0;
+  RGF_HIP(hipGetDevice(&dev));
+  const int chunk = chunk_for(Mp, nE);
   // Several lanes: each takes a contiguous share of the energies on its own
   // stream, driven by its own host thread, so one lane's latency-bound steps
   // (pivot panels, decimation convergence checks) overlap the other lanes'
   // matrix-core products.  Every per-energy step is independent of the
   // other energies, so the results equal those of a single lane bitwise.
   std::vector<Lane>& lanes = lane_streams(dev, nl);
+  std::lock_guard<std::mutex> lk(lane_mutex(dev));  // one multi-lane call at a time per device
   RGF_HIP(hipEventRecord(lanes[0].fork, st));
   std::vector<std::thread> th;
   std::vector<Error> errs(nl, Error{RGF_OK, ""});
@@ -248,7 +441,7 @@ void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double 
       try {
         RGF_HIP(hipSetDevice(dev));
         RGF_HIP(hipStreamWaitEvent(lanes[i].st, lanes[0].fork, 0));
-        run_range(lo, hi, lane_chunk, lanes[i].st);
+        run_range(d, E, lo, hi, eta, precision, T, info, lane_chunk, lanes[i].st, u_l, u_r);
         RGF_HIP(hipEventRecord(lanes[i].done, lanes[i].st));
       } catch (const Error& e) {
         errs[i] = e;
@@ -261,6 +454,111 @@ void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double 
   for (int i = 0; i < nl; ++i) {
     if (errs[i].code != RGF_OK) throw errs[i];
     RGF_HIP(hipStreamWaitEvent(st, lanes[i].done, 0));
+  }
+}
+
+// ------------------------------------------------------- many devices
+// Job list of the persistent small-block launch, per (device, stream): the
+// buffer is reused once the previous launch from it has finished.
+struct JobBuf {
+  void* p = nullptr;     // device copy
+  void* host = nullptr;  // pinned staging of the same size
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+};
+static std::mutex g_job_mu;
+static std::map<std::pair<int, hipStream_t>, JobBuf> g_jobs;
+
+static std::mutex& batch_mutex(int dev) {
+  static std::mutex mus[64];
+  return mus[dev & 63];
+}
+
+void transmission_batch_impl(const rgf_device* devs, int ndev, const double* const* E, const int64_t* nE,
+                             double eta, int precision, double* const* T, int32_t* const* info, hipStream_t st) {
+  int dev = 0;
+  RGF_HIP(hipGetDevice(&dev));
+  std::vector<int> big;
+  std::vector<SmallJob> jobs;
+  int64_t total = 0;
+  for (int d = 0; d < ndev; ++d) {
+    if (nE[d] == 0) continue;
+    if (uses_small_path(devs[d].M, precision)) {
+      SmallJob j;
+      j.a = small_args(devs[d], E[d], nE[d], eta, T[d], info ? info[d] : nullptr);
+      j.item0 = total;
+      total += nE[d];
+      jobs.push_back(j);
+    } else {
+      big.push_back(d);
+    }
+  }
+  // ---- small blocks: one persistent launch over every (device, energy) item ----
+  if (!jobs.empty()) {
+    const size_t need = sizeof(SmallJob) * jobs.size() + sizeof(unsigned long long);
+    std::lock_guard<std::mutex> lk(g_job_mu);
+    JobBuf& jb = g_jobs[{dev, st}];
+    if (!jb.done) RGF_HIP(hipEventCreateWithFlags(&jb.done, hipEventDisableTiming));
+    RGF_HIP(hipEventSynchronize(jb.done));  // the previous copy and launch from these buffers are done
+    if (jb.bytes < need) {
+      if (jb.p) RGF_HIP(hipFree(jb.p));
+      if (jb.host) RGF_HIP(hipHostFree(jb.host));
+      jb.p = jb.host = nullptr;
+      jb.bytes = 0;
+      RGF_HIP(hipMalloc(&jb.p, need));
+      RGF_HIP(hipHostMalloc(&jb.host, need, hipHostMallocDefault));
+      jb.bytes = need;
+    }
+    char* host = static_cast<char*>(jb.host);
+    std::memcpy(host, jobs.data(), sizeof(SmallJob) * jobs.size());
+    std::memset(host + sizeof(SmallJob) * jobs.size(), 0, sizeof(unsigned long long));  // the work counter
+    RGF_HIP(hipMemcpyAsync(jb.p, host, need, hipMemcpyHostToDevice, st));
+    auto* dj = static_cast<SmallJob*>(jb.p);
+    auto* counter = reinterpret_cast<unsigned long long*>(static_cast<char*>(jb.p) + sizeof(SmallJob) * jobs.size());
+    const int grid = (int)std::min<int64_t>(total, 512);  // two 64 KiB-LDS workgroups per CU
+    launch_small_queue(dj, (int)jobs.size(), total, counter, grid, st);
+    RGF_HIP(hipEventRecord(jb.done, st));
+  }
+  if (big.empty()) return;
+  // ---- larger blocks: the costliest device first, on worker streams ----
+  std::sort(big.begin(), big.end(), [&](int a, int b) {
+    const double ca = (double)devs[a].N * nE[a] * std::pow((double)round_up(devs[a].M, 64), 3.0);
+    const double cb = (double)devs[b].N * nE[b] * std::pow((double)round_up(devs[b].M, 64), 3.0);
+    return ca > cb || (ca == cb && a < b);
+  });
+  if (big.size() == 1) {
+    const int d = big[0];
+    transmission_impl(devs[d], E[d], nE[d], eta, precision, T[d], info ? info[d] : nullptr, st);
+    return;
+  }
+  const int nw = 2;
+  std::vector<Lane>& ws = lane_streams(dev, nw, true);
+  std::lock_guard<std::mutex> lk(batch_mutex(dev));  // one multi-device call at a time per device
+  RGF_HIP(hipEventRecord(ws[0].fork, st));
+  std::atomic<int> next{0};
+  std::vector<Error> errs(nw, Error{RGF_OK, ""});
+  std::vector<std::thread> th;
+  for (int w = 0; w < nw; ++w) {
+    th.emplace_back([&, w] {
+      try {
+        RGF_HIP(hipSetDevice(dev));
+        RGF_HIP(hipStreamWaitEvent(ws[w].st, ws[0].fork, 0));
+        for (int i = next++; i < (int)big.size(); i = next++) {
+          const int d = big[i];
+          run_device(devs[d], E[d], nE[d], eta, precision, T[d], info ? info[d] : nullptr, ws[w].st, 1.0 / nw);
+        }
+        RGF_HIP(hipEventRecord(ws[w].done, ws[w].st));
+      } catch (const Error& e) {
+        errs[w] = e;
+      } catch (const std::exception& e) {
+        errs[w] = Error{RGF_EDEVICE, e.what()};
+      }
+    });
+  }
+  for (auto& t : th) t.join();
+  for (int w = 0; w < nw; ++w) {
+    if (errs[w].code != RGF_OK) throw errs[w];
+    RGF_HIP(hipStreamWaitEvent(st, ws[w].done, 0));
   }
 }
 
@@ -312,15 +610,47 @@ int rgf_transmission(const rgf_device* dev, const double* E, int64_t nE, double 
                      int32_t* info, void* stream) {
   return guarded([&] {
     RGF_CHECK(dev, RGF_EINVAL, "null device");
-    RGF_CHECK(dev->N >= 1, RGF_EINVAL, "N < 1");
-    RGF_CHECK(dev->M >= 1 && dev->M <= MAX_M, RGF_EINVAL, "M must be in [1, 2048]");
-    RGF_CHECK(dev->Hd && dev->Sd, RGF_EINVAL, "null device block pointer");
-    RGF_CHECK(dev->N == 1 || (dev->Hu && dev->Su), RGF_EINVAL, "null coupling block pointer");
-    check_lead(dev->left, dev->M, "left lead");
-    check_lead(dev->right, dev->M, "right lead");
+    check_device(*dev);
     check_common(E, nE, eta, precision, T);
     if (nE == 0) return;
     transmission_impl(*dev, E, nE, eta, precision, T, info, (hipStream_t)stream);
+  });
+}
+
+int rgf_transmission_bias(const rgf_device* dev, const double* E, int64_t nE, double eta, double u_left,
+                          double u_right, int precision, double* T, int32_t* info, void* stream) {
+  return guarded([&] {
+    RGF_CHECK(dev, RGF_EINVAL, "null device");
+    check_device(*dev);
+    check_common(E, nE, eta, precision, T);
+    RGF_CHECK(std::isfinite(u_left) && std::isfinite(u_right), RGF_EINVAL, "electrode shifts must be finite");
+    if (nE == 0) return;
+    transmission_impl(*dev, E, nE, eta, precision, T, info, (hipStream_t)stream, u_left, u_right);
+  });
+}
+
+int rgf_landauer_current(const double* E, const double* T, int64_t nE, double mu_left, double mu_right, double kT,
+                         double* I, void* stream) {
+  return guarded([&] {
+    RGF_CHECK(nE >= 0, RGF_EINVAL, "nE < 0");
+    RGF_CHECK(I && (nE == 0 || (E && T)), RGF_EINVAL, "null energy, transmission or output pointer");
+    RGF_CHECK(std::isfinite(mu_left) && std::isfinite(mu_right), RGF_EINVAL, "chemical potentials must be finite");
+    RGF_CHECK(std::isfinite(kT) && kT >= 0.0, RGF_EINVAL, "kT must be finite and >= 0");
+    launch_landauer(E, T, nE, mu_left, mu_right, kT, I, (hipStream_t)stream);
+  });
+}
+
+int rgf_transmission_batch(const rgf_device* devs, int32_t ndev, const double* const* E, const int64_t* nE,
+                           double eta, int precision, double* const* T, int32_t* const* info, void* stream) {
+  return guarded([&] {
+    RGF_CHECK(ndev >= 0, RGF_EINVAL, "ndev < 0");
+    if (ndev == 0) return;
+    RGF_CHECK(devs && E && nE && T, RGF_EINVAL, "null device, energy, count or output array");
+    for (int d = 0; d < ndev; ++d) {
+      check_device(devs[d]);
+      check_common(E[d], nE[d], eta, precision, T[d]);
+    }
+    transmission_batch_impl(devs, ndev, E, nE, eta, precision, T, info, (hipStream_t)stream);
   });
 }
 
@@ -345,9 +675,22 @@ int rgf_release_workspaces(void) {
     for (auto it = g_ws.begin(); it != g_ws.end();) {
       if (it->first.first == dev) {
         RGF_HIP(hipDeviceSynchronize());
+        if (it->second.base) drop_graphs_on(it->second.base);
         if (it->second.base) RGF_HIP(hipFree(it->second.base));
         if (it->second.host_active) RGF_HIP(hipHostFree(it->second.host_active));
         it = g_ws.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    std::lock_guard<std::mutex> lj(g_job_mu);
+    for (auto it = g_jobs.begin(); it != g_jobs.end();) {
+      if (it->first.first == dev) {
+        if (it->second.done) RGF_HIP(hipEventSynchronize(it->second.done));
+        if (it->second.p) RGF_HIP(hipFree(it->second.p));
+        if (it->second.host) RGF_HIP(hipHostFree(it->second.host));
+        if (it->second.done) RGF_HIP(hipEventDestroy(it->second.done));
+        it = g_jobs.erase(it);
       } else {
         ++it;
       }
@@ -388,7 +731,7 @@ int rgf_get_tile(int precision, int32_t* tile) {
   return guarded([&] {
     RGF_CHECK(tile, RGF_EINVAL, "null tile pointer");
     RGF_CHECK(precision == RGF_FP64 || precision == RGF_MIXED, RGF_EINVAL, "unknown precision");
-    *tile = g_tile[precision == RGF_FP64 ? 0 : 1];
+    *tile = g_tile_default[precision == RGF_FP64 ? 0 : 1].load();
   });
 }
 
@@ -396,7 +739,39 @@ int rgf_set_tile(int precision, int32_t tile) {
   return guarded([&] {
     RGF_CHECK(precision == RGF_FP64 || precision == RGF_MIXED, RGF_EINVAL, "unknown precision");
     RGF_CHECK(tile == 64 || tile == 128, RGF_EINVAL, "tile must be 64 or 128");
-    g_tile[precision == RGF_FP64 ? 0 : 1] = tile;
+    const int p = precision == RGF_FP64 ? 0 : 1;
+    g_tile_default[p] = tile;
+    for (auto& t : g_tune_tile[p]) t = 0;  // a global tile replaces any per-size choice
+  });
+}
+
+int rgf_set_graphs(int enable) {
+  return guarded([&] { g_graphs_on = enable ? 1 : 0; });
+}
+
+int rgf_get_graphs(void) { return graphs_enabled() ? 1 : 0; }
+
+int rgf_get_tuning(int32_t M, int precision, int32_t* tile, int32_t* lanes) {
+  return guarded([&] {
+    RGF_CHECK(M >= 1 && M <= MAX_M, RGF_EINVAL, "M must be in [1, 2048]");
+    RGF_CHECK(precision == RGF_FP64 || precision == RGF_MIXED, RGF_EINVAL, "unknown precision");
+    const int prec = precision == RGF_FP64 ? PREC_F64 : PREC_F32;
+    const int Mp = (int)round_up(M, 64);
+    if (tile) *tile = tile_for(prec, Mp);
+    if (lanes) *lanes = lanes_for(Mp, prec);
+  });
+}
+
+int rgf_set_tuning(int32_t M, int precision, int32_t tile, int32_t lanes) {
+  return guarded([&] {
+    RGF_CHECK(M >= 1 && M <= MAX_M, RGF_EINVAL, "M must be in [1, 2048]");
+    RGF_CHECK(precision == RGF_FP64 || precision == RGF_MIXED, RGF_EINVAL, "unknown precision");
+    RGF_CHECK(tile == 0 || tile == 64 || tile == 128, RGF_EINVAL, "tile must be 0, 64 or 128");
+    RGF_CHECK(lanes >= 0 && lanes <= 4, RGF_EINVAL, "lanes must be in [0, 4]");
+    const int p = precision == RGF_FP64 ? 0 : 1;
+    const int k = (int)round_up(M, 64) / 64;
+    g_tune_tile[p][k] = tile;
+    g_tune_lanes[p][k] = lanes;
   });
 }
 

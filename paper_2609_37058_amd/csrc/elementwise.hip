@@ -190,7 +190,117 @@ __global__ void sr_info_kernel(const int32_t* done, int32_t bit, const int32_t* 
 
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + ET - 1) / ET); }
 
+// Counter-based pseudo-random fill (SplitMix64 of seed + index): entries
+// scale * (u + i v) with u, v uniform in [-1, 1), plus `diag` on the diagonal
+// of each rows x ld block.  Synthetic inputs for tuning only.
+__global__ void random_kernel(z64* p, int64_t n, int64_t ld, int64_t rows, double scale, double diag,
+                              uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  auto mix = [](uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+  };
+  const uint64_t h1 = mix(seed + 2 * (uint64_t)i), h2 = mix(seed + 2 * (uint64_t)i + 1);
+  const double u = (double)(h1 >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  const double v = (double)(h2 >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  const int64_t r = (i / ld) % rows, c = i % ld;
+  p[i] = zmake(scale * u + (r == c ? diag : 0.0), scale * v);
+}
+
+
+
+__global__ void shift_kernel(double* dst, const double* src, int64_t n, double u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i] - u;
+}
+
+// Fermi-Dirac occupation; kT = 0: the step, 1/2 exactly at E = mu
+__device__ inline double fermi(double E, double mu, double kT) {
+  if (kT == 0.0) return E < mu ? 1.0 : (E > mu ? 0.0 : 0.5);
+  const double x = (E - mu) / kT;
+  const double e = exp(-fabs(x));  // <= 1: no overflow on either side
+  return x > 0.0 ? e / (1.0 + e) : 1.0 / (1.0 + e);
+}
+
+constexpr int LT = 256;
+// Landauer integral in one workgroup: thread t sums the trapezoids of the
+// contiguous interval range [t*chunk, (t+1)*chunk) in order, then a fixed
+// binary tree in LDS; the result does not depend on the launch.
+__global__ __launch_bounds__(LT) void landauer_kernel(const double* E, const double* T, int64_t n, double mu_l,
+                                                      double mu_r, double kT, double g0, double* I) {
+  __shared__ double part[LT];
+  const int t = threadIdx.x;
+  const int64_t nint = n - 1;  // intervals
+  const int64_t chunk = (nint + LT - 1) / LT;
+  double s = 0.0;
+  const int64_t a = t * chunk, bnd = (a + chunk < nint) ? a + chunk : nint;
+  for (int64_t k = a; k < bnd; ++k) {
+    const double g0k = (fermi(E[k], mu_l, kT) - fermi(E[k], mu_r, kT)) * T[k];
+    const double g1k = (fermi(E[k + 1], mu_l, kT) - fermi(E[k + 1], mu_r, kT)) * T[k + 1];
+    s += (E[k + 1] - E[k]) * (g0k + g1k) * 0.5;
+  }
+  part[t] = s;
+  __syncthreads();
+  for (int w = LT / 2; w > 0; w >>= 1) {
+    if (t < w) part[t] += part[t + w];
+    __syncthreads();
+  }
+  if (t == 0) I[0] = g0 * part[0];
+}
+
+// X(k) block elements from the real-space images (HBM-bound: nR reads, one write per element)
+__global__ void bloch_kernel(BlochArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  z64 acc = zmake(0.0, 0.0);
+  for (int r = 0; r < a.nR; ++r)
+    if (a.src[r]) acc = zfma(a.w[r], a.src[r][i], acc);
+  a.dst[i] = acc;
+}
+
+__global__ void kaccum_kernel(double* T, const double* Tk, double w, int64_t n, int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) T[i] = (first ? 0.0 : T[i]) + w * Tk[i];
+}
+
 }  // namespace
+
+void launch_bloch(const BlochArgs& a, hipStream_t st) {
+  if (a.n <= 0) return;
+  hipLaunchKernelGGL(bloch_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_kaccum(double* T, const double* Tk, double w, int64_t n, int first, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(kaccum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, T, Tk, w, n, first);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_shift(double* dst, const double* src, int64_t n, double u, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(shift_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n, u);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_landauer(const double* E, const double* T, int64_t n, double mu_l, double mu_r, double kT, double* I,
+                     hipStream_t st) {
+  // 2 e^2 / h with the exact SI constants (C, J s): the spin-degenerate conductance quantum
+  const double e = 1.602176634e-19, h = 6.62607015e-34;
+  hipLaunchKernelGGL(landauer_kernel, dim3(1), dim3(LT), 0, st, E, T, n, mu_l, mu_r, kT, 2.0 * e * e / h, I);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_random(z64* p, int64_t n, int64_t ld, int64_t rows, double scale, double diag, uint64_t seed,
+                   hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(random_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, ld, rows, scale,
+                     diag, seed);
+  RGF_HIP(hipGetLastError());
+}
 
 void launch_fill(const FillArgs& a, int batch, hipStream_t st) {
   if (batch <= 0) return;

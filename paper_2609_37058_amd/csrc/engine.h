@@ -18,7 +18,11 @@ void profile_launch_begin(hipStream_t st);
 void profile_launch_end(hipStream_t st, double flops);
 bool profiling();
 
-int tile_for(int prec);
+constexpr int MAX_M = 2048;  // largest block size the library accepts
+
+// tuning table: block-product tile and energy lanes for (precision, padded size)
+int tile_for(int prec, int Mp);
+int lanes_for(int Mp, int prec);
 int mixed_parts();  // RGF_MIXED_* bits in effect for the mixed path
 
 // Device memory for `batch` energies at padded block size Mp.
@@ -28,6 +32,8 @@ struct Layout {
   size_t bytes = 0;
   // offsets (bytes) into the arena
   size_t sig, un, linv, uinv, perm, cand, flags, ints, dbl;
+  size_t energies, tout, iout;  // staged energies and sweep outputs (stable addresses for graphs)
+  size_t elead, erlead;         // energies of the left / right electrode when biased (E - u)
   static Layout make(int Mp, int batch);
 };
 
@@ -36,8 +42,15 @@ class Engine {
   Engine(char* arena, const Layout& lay, hipStream_t st, int prec, int M, const double* E, double eta,
          int32_t* host_active);
 
-  // decimation of `lead` for all energies of the chunk; leaves eps_L, eps_R
-  void decimate(const rgf_lead& lead, int32_t* done);
+  // The lead steps run at the chunk's energies, or at energies given per side:
+  // an electrode rigidly shifted by u (H -> H + u S) is the unshifted one at E - u.
+  void set_lead_energies(const double* EL, const double* ER) {
+    EL_ = EL;
+    ER_ = ER;
+  }
+  // decimation of `lead` for all energies of the chunk (those of side `left`);
+  // leaves eps_L, eps_R
+  void decimate(const rgf_lead& lead, int32_t* done, bool left = true);
   // sigma = L (eps_L^-1 U) for the left side, U (eps_R^-1 L) for the right side
   void self_energy(const rgf_lead& lead, bool left, z64* out);
   // Gamma_L, Gamma_R from Sigma_L, Sigma_R
@@ -64,6 +77,7 @@ class Engine {
   hipStream_t st_;
   int prec_, M_, Mp_, B_;
   const double* E_;
+  const double *EL_, *ER_;  // lead energies per side (E_ unless shifted)
   double eta_;
   int64_t MM_;
   int nblk_sr_;
@@ -75,5 +89,17 @@ class Engine {
   double *scale_, *partial_;
   int32_t* host_active_;
 };
+
+// ---- one device through the path (api.hip) ----
+void check_device(const rgf_device& d);
+bool uses_small_path(int M, int precision);
+SmallArgs small_args(const rgf_device& d, const double* E, int64_t nE, double eta, double* T, int32_t* info);
+// the whole path for one device on one stream (no lanes); mem_share scales the
+// workspace budget when several devices run side by side
+// u_l, u_r: rigid shifts of the left / right electrode (finite bias; 0 at zero bias)
+void run_device(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
+                int32_t* info, hipStream_t st, double mem_share, double u_l = 0.0, double u_r = 0.0);
+void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
+                       int32_t* info, hipStream_t st, double u_l = 0.0, double u_r = 0.0);
 
 }  // namespace rgf

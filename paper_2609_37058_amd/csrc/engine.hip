@@ -57,13 +57,19 @@ Layout Layout::make(int Mp, int batch) {
   l.flags = take((size_t)batch * Mp);
   l.ints = take((size_t)(4 * batch + 64) * 4);
   l.dbl = take((size_t)(batch + batch * l.nblk_sr * 2) * 8);
+  l.energies = take((size_t)batch * 8);
+  l.tout = take((size_t)batch * 8);
+  l.iout = take((size_t)batch * 4);
+  l.elead = take((size_t)batch * 8);
+  l.erlead = take((size_t)batch * 8);
   l.bytes = off;
   return l;
 }
 
 Engine::Engine(char* arena, const Layout& lay, hipStream_t st, int prec, int M, const double* E, double eta,
                int32_t* host_active)
-    : st_(st), prec_(prec), M_(M), Mp_(lay.Mp), B_(lay.batch), E_(E), eta_(eta), host_active_(host_active) {
+    : st_(st), prec_(prec), M_(M), Mp_(lay.Mp), B_(lay.batch), E_(E), EL_(E), ER_(E), eta_(eta),
+      host_active_(host_active) {
   MM_ = (int64_t)Mp_ * Mp_;
   nblk_sr_ = lay.nblk_sr;
   const int64_t U = (int64_t)B_ * MM_;
@@ -116,11 +122,11 @@ double Engine::gemm(GemmArgs g, int prec, bool timed) {
   const int role = timed ? 1 : 0;
   if (timed && profiling()) {
     profile_launch_begin(st_);
-    double f = launch_gemm(g, prec, tile_for(prec), st_, role);
+    double f = launch_gemm(g, prec, tile_for(prec, Mp_), st_, role);
     profile_launch_end(st_, f);
     return f;
   }
-  return launch_gemm(g, prec, tile_for(prec), st_, role);
+  return launch_gemm(g, prec, tile_for(prec, Mp_), st_, role);
 }
 
 static GemmArgs gemm_args(int rows, int cols, int K, int batch) {
@@ -160,14 +166,15 @@ FillArgs Engine::fill_args(MatRef dst, int rows, int cols, int kind) const {
   return f;
 }
 
-void Engine::decimate(const rgf_lead& lead, int32_t* done) {
+void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
   const int Mp = Mp_;
-  const int tile = tile_for(PREC_F64);
+  const double* El = left ? EL_ : ER_;
+  const int tile = tile_for(PREC_F64, Mp_);
   RGF_HIP(hipMemsetAsync(done, 0, sizeof(int32_t) * B_, st_));
   RGF_HIP(hipMemsetAsync(iters_, 0, sizeof(int32_t) * B_, st_));
   // eps = eps_L = eps_R = D (identity padding), alpha = U, beta = L
   FillArgs f = fill_args(mref(eps_, Mp, MM_), Mp, Mp, FILL_FORM);
-  f.f = form(lead.H00, lead.S00, M_, false, true, E_, eta_);
+  f.f = form(lead.H00, lead.S00, M_, false, true, El, eta_);
   launch_fill(f, B_, st_);
   f = fill_args(mref(epsL_, Mp, MM_), Mp, Mp, FILL_MAT);
   f.src = mref(eps_, Mp, MM_);
@@ -175,7 +182,7 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done) {
   f.dst = mref(epsR_, Mp, MM_);
   launch_fill(f, B_, st_);
   f = fill_args(mref(AB_, Mp, 2 * MM_), Mp, Mp, FILL_FORM);
-  f.f = form(lead.H01, lead.S01, M_, false, false, E_, eta_);
+  f.f = form(lead.H01, lead.S01, M_, false, false, El, eta_);
   launch_fill(f, B_, st_);
   f.dst = mref(AB_ + MM_, Mp, 2 * MM_);
   f.f.conj_t = 1;
@@ -227,21 +234,22 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done) {
 
 void Engine::self_energy(const rgf_lead& lead, bool left, z64* out) {
   const int Mp = Mp_;
-  const int tile = tile_for(PREC_F64);
+  const int tile = tile_for(PREC_F64, Mp_);
   FillArgs f = fill_args(mref(Tsr_, Mp, MM_), Mp, Mp, FILL_MAT);
   f.src = mref(left ? epsL_ : epsR_, Mp, MM_);
   launch_fill(f, B_, st_);
   lu_factor(lu_, Tsr_, MM_, Mp, B_, nullptr, SING_LEAD, PREC_F64, tile, st_);
   // RHS: U of the lead (left side) or L (right side), rows gathered by the pivots
   f = fill_args(mref(Ysr_, Mp, 2 * MM_), Mp, Mp, FILL_FORM);
-  f.f = form(lead.H01, lead.S01, M_, /*conj_t=*/!left, false, E_, eta_);
+  const double* El = left ? EL_ : ER_;
+  f.f = form(lead.H01, lead.S01, M_, /*conj_t=*/!left, false, El, eta_);
   f.ridx = lu_.perm;
   f.ridx_bs = Mp;
   launch_fill(f, B_, st_);
   lu_solve(lu_, Tsr_, MM_, Mp, Ysr_, 2 * MM_, Mp, B_, nullptr, PREC_F64, tile, st_);
   GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
   g.a_kind = SRC_FORM;
-  g.Af = form(lead.H01, lead.S01, M_, /*conj_t=*/left, false, E_, eta_);
+  g.Af = form(lead.H01, lead.S01, M_, /*conj_t=*/left, false, El, eta_);
   g.B = mref(Ysr_, Mp, 2 * MM_);
   g.C = mref(out, Mp, MM_);
   gemm(g, PREC_F64, false);
@@ -262,7 +270,7 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
   const int sp = (mask & 1) ? PREC_F32 : PREC_F64;
   const int lp = (mask & 2) ? PREC_F32 : PREC_F64;
   const int tp = (mask & 4) ? PREC_F32 : PREC_F64;
-  const int tile = tile_for(sp);
+  const int tile = tile_for(sp, Mp_);
   const MatRef X = mref(Y_, Mp, MM_);
 
   // B_0 = A_00 - Sigma_L (- Sigma_R when N = 1)

@@ -19,9 +19,19 @@ struct SmallArgs {
   int32_t* info;
   double sr_tol;
   int sr_maxit;
+  double u_l, u_r;  // rigid shifts of the electrodes: each lead runs at z - u
 };
 constexpr int SMALL_MAX_M = 16;
 void launch_small(const SmallArgs& a, hipStream_t st);
+// one device's energies [item0, item0 + a.nE) of a persistent multi-device launch
+struct SmallJob {
+  SmallArgs a;
+  int64_t item0;
+};
+// persistent launch of `grid` workgroups over `total` items of the jobs (device
+// memory, item0 ascending); *counter must be 0 on entry
+void launch_small_queue(const SmallJob* jobs, int njobs, int64_t total, unsigned long long* counter, int grid,
+                        hipStream_t st);
 
 // ---------------------------------------------------------- block products
 // C[b] = Cin[b] + alpha * opA[b] * opB[b], complex, for rows x cols outputs
@@ -105,6 +115,29 @@ struct FillArgs {
   BatchCtl ctl;
 };
 void launch_fill(const FillArgs& a, int batch, hipStream_t st);
+// synthetic inputs: p[i] = scale (u + i v) (+ diag on block diagonals), u, v uniform in [-1, 1)
+void launch_random(z64* p, int64_t n, int64_t ld, int64_t rows, double scale, double diag, uint64_t seed,
+                   hipStream_t st);
+
+// Bloch sum over transverse images: dst[i] = sum_r w[r] src[r][i] (null src[r]: a zero block)
+constexpr int MAX_IMAGES = 32;
+struct BlochArgs {
+  const z64* src[MAX_IMAGES];
+  z64 w[MAX_IMAGES];
+  int nR;
+  z64* dst;
+  int64_t n;
+};
+void launch_bloch(const BlochArgs& a, hipStream_t st);
+// T[e] = (first ? 0 : T[e]) + w * Tk[e]: the k-point average, accumulated in mesh order
+void launch_kaccum(double* T, const double* Tk, double w, int64_t n, int first, hipStream_t st);
+
+// dst[k] = src[k] - u, k < n (energies of a rigidly shifted electrode)
+void launch_shift(double* dst, const double* src, int64_t n, double u, hipStream_t st);
+// I[0] = G0 * trapezoid over the ascending E of (f(E, mu_L) - f(E, mu_R)) T, one workgroup,
+// fixed summation order
+void launch_landauer(const double* E, const double* T, int64_t n, double mu_l, double mu_r, double kT, double* I,
+                     hipStream_t st);
 
 // dst[b] += s * src[b] (rows x cols)
 void launch_axpy(MatRef dst, MatRef src, double s, int rows, int cols, int batch, BatchCtl ctl,

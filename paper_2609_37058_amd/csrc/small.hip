@@ -17,6 +17,8 @@
 //                = Re Tr[Gamma_L G Gamma_R G^+]
 // Each solve is Gauss-Jordan elimination with partial pivoting (largest
 // |Re|+|Im|, lowest row on ties) on the augmented block [B | RHS].
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -190,10 +192,8 @@ __device__ void broadening(int M, const z64* sig, z64* gam) {
 
 }  // namespace
 
-__global__ __launch_bounds__(SM_T) void rgf_small_kernel(SmallArgs a) {
-  const int k = blockIdx.x;
-  if (k >= a.nE) return;
-  __shared__ z64 sm[13 * SM_MM + SM_MAX * 3 * SM_MAX];
+// The whole path for energy k of one device (one wavefront, blocks in `sm`).
+__device__ void small_solve(const SmallArgs& a, int k, z64* sm) {
   const int M = a.M;
   Bufs b;
   b.eps = sm;
@@ -215,14 +215,16 @@ __global__ __launch_bounds__(SM_T) void rgf_small_kernel(SmallArgs a) {
   int32_t info = 0;
   bool sing_lead = false, conv_l = false, conv_r = false;
 
-  sancho_rubio(M, a.LH00, a.LH01, a.LS00, a.LS01, z, a.sr_tol, a.sr_maxit, b, &conv_l, &sing_lead);
-  self_energy(M, a.LH01, a.LS01, z, b.epsL, true, b, b.sigL, &sing_lead);
-  if (a.same_leads) {
+  // a rigidly shifted electrode (H -> H + u S) is the unshifted one at z - u
+  const z64 zl = zmake(z.x - a.u_l, z.y), zr = zmake(z.x - a.u_r, z.y);
+  sancho_rubio(M, a.LH00, a.LH01, a.LS00, a.LS01, zl, a.sr_tol, a.sr_maxit, b, &conv_l, &sing_lead);
+  self_energy(M, a.LH01, a.LS01, zl, b.epsL, true, b, b.sigL, &sing_lead);
+  if (a.same_leads && a.u_l == a.u_r) {
     conv_r = conv_l;
   } else {
-    sancho_rubio(M, a.RH00, a.RH01, a.RS00, a.RS01, z, a.sr_tol, a.sr_maxit, b, &conv_r, &sing_lead);
+    sancho_rubio(M, a.RH00, a.RH01, a.RS00, a.RS01, zr, a.sr_tol, a.sr_maxit, b, &conv_r, &sing_lead);
   }
-  self_energy(M, a.RH01, a.RS01, z, b.epsR, false, b, b.sigR, &sing_lead);
+  self_energy(M, a.RH01, a.RS01, zr, b.epsR, false, b, b.sigR, &sing_lead);
   broadening(M, b.sigL, b.gamL);
   broadening(M, b.sigR, b.gamR);
   if (!conv_l) info |= RGF_INFO_SR_LEFT;
@@ -289,9 +291,52 @@ __global__ __launch_bounds__(SM_T) void rgf_small_kernel(SmallArgs a) {
   }
 }
 
+
+constexpr int SM_LDS = 13 * SM_MM + SM_MAX * 3 * SM_MAX;
+
+__global__ __launch_bounds__(SM_T) void rgf_small_kernel(SmallArgs a) {
+  const int k = blockIdx.x;
+  if (k >= a.nE) return;
+  __shared__ z64 sm[SM_LDS];
+  small_solve(a, k, sm);
+}
+
+// Persistent form over many devices: every workgroup takes (device, energy)
+// items from a global counter until the list is exhausted, so devices of
+// uneven block size, length and energy count share one launch and the
+// workgroups stay busy until the last item.
+__global__ __launch_bounds__(SM_T) void rgf_small_queue_kernel(const SmallJob* jobs, int njobs, int64_t total,
+                                                                unsigned long long* counter) {
+  __shared__ z64 sm[SM_LDS];
+  __shared__ long long sh_item;
+  for (;;) {
+    if (threadIdx.x == 0) sh_item = (long long)atomicAdd(counter, 1ull);
+    bar();
+    const long long item = sh_item;
+    bar();  // every lane has the item before lane 0 takes the next one
+    if (item >= total) return;
+    int lo = 0, hi = njobs - 1;  // the last job whose first item is <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (jobs[mid].item0 <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    small_solve(jobs[lo].a, (int)(item - jobs[lo].item0), sm);
+    bar();
+  }
+}
+
 void launch_small(const SmallArgs& a, hipStream_t st) {
   if (a.nE <= 0) return;
   hipLaunchKernelGGL(rgf_small_kernel, dim3((unsigned)a.nE), dim3(SM_T), 0, st, a);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_small_queue(const SmallJob* jobs, int njobs, int64_t total, unsigned long long* counter, int grid,
+                        hipStream_t st) {
+  if (total <= 0 || njobs <= 0) return;
+  hipLaunchKernelGGL(rgf_small_queue_kernel, dim3((unsigned)std::max(1, grid)), dim3(SM_T), 0, st, jobs, njobs,
+                     total, counter);
   RGF_HIP(hipGetLastError());
 }
 

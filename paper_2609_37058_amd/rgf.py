@@ -72,6 +72,23 @@ SIGNATURES = {
     "rgf_set_mixed_parts": (C.c_int, [C.c_int]),
     "rgf_get_mixed_parts": (C.c_int, []),
     "rgf_set_tile": (C.c_int, [C.c_int, C.c_int32]),
+    "rgf_transmission_bias": (C.c_int, [C.POINTER(rgf_device), C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                                        C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rgf_landauer_current": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                       C.c_void_p, C.c_void_p]),
+    "rgf_transmission_kmesh": (C.c_int, [C.POINTER(rgf_device), C.c_int32, C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.c_void_p,
+                                         C.c_int64, C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]),
+    "rgf_set_graphs": (C.c_int, [C.c_int]),
+    "rgf_get_graphs": (C.c_int, []),
+    "rgf_get_tuning": (C.c_int, [C.c_int32, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "rgf_set_tuning": (C.c_int, [C.c_int32, C.c_int, C.c_int32, C.c_int32]),
+    "rgf_autotune": (C.c_int, [C.c_int32, C.c_int, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                               C.POINTER(C.c_double)]),
+    "rgf_transmission_batch": (C.c_int, [C.POINTER(rgf_device), C.c_int32, C.POINTER(C.c_void_p),
+                                         C.POINTER(C.c_int64), C.c_double, C.c_int, C.POINTER(C.c_void_p),
+                                         C.POINTER(C.c_void_p), C.c_void_p]),
 }
 
 
@@ -173,6 +190,93 @@ def transmission(dev: DeviceTensors, E: torch.Tensor, eta: float, precision="fp6
     return out, info
 
 
+def transmission_bias(dev: DeviceTensors, E: torch.Tensor, eta: float, u_left: float, u_right: float,
+                      precision="fp64", stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """T(E, V_b) with the zero-bias device and electrodes rigidly shifted by u_left / u_right (eV)."""
+    lib = load()
+    E = E.contiguous()
+    nE = E.numel()
+    out = torch.empty(nE, dtype=torch.float64, device=E.device)
+    info = torch.empty(nE, dtype=torch.int32, device=E.device)
+    d = dev.cstruct()
+    _check(lib.rgf_transmission_bias(C.byref(d), _ptr(E), nE, float(eta), float(u_left), float(u_right),
+                                     PRECISION[precision], _ptr(out), _ptr(info), _stream(stream)))
+    return out, info
+
+
+def landauer_current(E: torch.Tensor, T: torch.Tensor, mu_left: float, mu_right: float, kT: float,
+                     stream=None) -> torch.Tensor:
+    """I (amperes, a one-element device tensor) = G0 * trapezoid of (f_L - f_R) T over the ascending E."""
+    lib = load()
+    E = E.contiguous()
+    T = T.contiguous()
+    if E.numel() != T.numel():
+        raise ValueError("E and T differ in length")
+    I = torch.empty(1, dtype=torch.float64, device=E.device)
+    _check(lib.rgf_landauer_current(_ptr(E), _ptr(T), E.numel(), float(mu_left), float(mu_right), float(kT),
+                                    _ptr(I), _stream(stream)))
+    return I
+
+
+def current(dev: DeviceTensors, E: torch.Tensor, eta: float, e_fermi: float, v_bias: float, kT: float,
+            precision="fp64", stream=None):
+    """Symmetric bias: (T(E, V_b), info, I) with mu_L,R = E_F +- V_b/2 and electrodes shifted by +-V_b/2."""
+    T, info = transmission_bias(dev, E, eta, v_bias / 2.0, -v_bias / 2.0, precision, stream)
+    I = landauer_current(E, T, e_fermi + v_bias / 2.0, e_fermi - v_bias / 2.0, kT, stream)
+    return T, info, I
+
+
+def transmission_kmesh(images, R, kpts, weights, E: torch.Tensor, eta: float, precision="fp64", stream=None):
+    """k-averaged T(E) over a transverse mesh from real-space images.
+
+    images: list of DeviceTensors (one per lattice image R[r]); R: [nR, 2] ints;
+    kpts: [nk, 2] fractional; weights: [nk].  Returns (T [nE], Tk [nk, nE], info [nk, nE]).
+    """
+    import numpy as np
+    lib = load()
+    R = np.ascontiguousarray(R, dtype=np.int32).reshape(-1, 2)
+    kpts = np.ascontiguousarray(kpts, dtype=np.float64).reshape(-1, 2)
+    weights = np.ascontiguousarray(weights, dtype=np.float64)
+    nR, nk = len(R), len(kpts)
+    if len(images) != nR or len(weights) != nk:
+        raise ValueError("one image per lattice vector and one weight per k-point")
+    E = E.contiguous()
+    nE = E.numel()
+    T = torch.empty(nE, dtype=torch.float64, device=E.device)
+    Tk = torch.empty((nk, nE), dtype=torch.float64, device=E.device)
+    info = torch.empty((nk, nE), dtype=torch.int32, device=E.device)
+    cimg = (rgf_device * nR)(*[im.cstruct() for im in images])
+    _check(lib.rgf_transmission_kmesh(cimg, nR, R.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      kpts.ctypes.data_as(C.POINTER(C.c_double)),
+                                      weights.ctypes.data_as(C.POINTER(C.c_double)), nk, _ptr(E), nE, float(eta),
+                                      PRECISION[precision], _ptr(T), _ptr(Tk), _ptr(info), _stream(stream)))
+    return T, Tk, info
+
+
+def transmission_batch(devs, Es, eta: float, precision="fp64", stream=None):
+    """T(E) of several devices of uneven (N, M) and energy counts in one call.
+
+    devs: list of DeviceTensors; Es: list of float64 device tensors.  Returns a list
+    of (T, info) device tensors.  Stream-ordered like the C call.
+    """
+    lib = load()
+    n = len(devs)
+    if len(Es) != n:
+        raise ValueError("one energy tensor per device")
+    Es = [E.contiguous() for E in Es]
+    outs = [torch.empty(E.numel(), dtype=torch.float64, device=E.device) for E in Es]
+    infos = [torch.empty(E.numel(), dtype=torch.int32, device=E.device) for E in Es]
+    cdevs = (rgf_device * max(n, 1))(*[d.cstruct() for d in devs])
+    P = C.c_void_p * max(n, 1)
+    e_ptrs = P(*[_ptr(E) for E in Es])
+    t_ptrs = P(*[_ptr(t) for t in outs])
+    i_ptrs = P(*[_ptr(i) for i in infos])
+    counts = (C.c_int64 * max(n, 1))(*[E.numel() for E in Es])
+    _check(lib.rgf_transmission_batch(cdevs, n, e_ptrs, counts, float(eta), PRECISION[precision], t_ptrs,
+                                      i_ptrs, _stream(stream)))
+    return list(zip(outs, infos))
+
+
 def lead_self_energy(lead: LeadTensors, side: int, E: torch.Tensor, eta: float, precision="fp64",
                      stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Sigma[nE, M, M] of one lead (side RGF_LEFT: L g_L U, RGF_RIGHT: U g_R L) and info."""
@@ -212,6 +316,62 @@ def get_tile(precision="fp64") -> int:
 
 def set_tile(precision, tile: int):
     _check(load().rgf_set_tile(PRECISION[precision], int(tile)))
+
+
+def set_graphs(enable: bool):
+    """Capture each chunk's sweep into a HIP graph on first use and replay it on later calls."""
+    _check(load().rgf_set_graphs(1 if enable else 0))
+
+
+def get_graphs() -> bool:
+    return bool(load().rgf_get_graphs())
+
+
+def get_tuning(M: int, precision="fp64") -> Tuple[int, int]:
+    """(tile, lanes) in effect for block size M (defaults resolved)."""
+    t, n = C.c_int32(), C.c_int32()
+    _check(load().rgf_get_tuning(int(M), PRECISION[precision], C.byref(t), C.byref(n)))
+    return t.value, n.value
+
+
+def set_tuning(M: int, precision, tile: int = 0, lanes: int = 0):
+    """Tile (0/64/128) and lanes (0..4) for block size M's class; 0 restores the default."""
+    _check(load().rgf_set_tuning(int(M), PRECISION[precision], int(tile), int(lanes)))
+
+
+def autotune(M: int, precision="fp64", batch: int = 64) -> dict:
+    """Time the (tile, lanes) choices for block size M on the GPU, keep the fastest.
+
+    Returns {"M", "precision", "tile", "lanes", "ms": {(tile, lanes): ms}}.
+    """
+    t, n = C.c_int32(), C.c_int32()
+    ms = (C.c_double * 4)()
+    _check(load().rgf_autotune(int(M), PRECISION[precision], int(batch), C.byref(t), C.byref(n), ms))
+    keys = [(64, 1), (64, 2), (128, 1), (128, 2)]
+    return {"M": int(M), "precision": precision, "tile": t.value, "lanes": n.value,
+            "ms": {k: ms[i] for i, k in enumerate(keys) if ms[i] >= 0}}
+
+
+def save_tuning(path: str, sizes, precisions=("fp64", "mixed")):
+    """Write the table entries in effect for the given block sizes to a JSON file."""
+    import json
+    rows = []
+    for M in sizes:
+        for p in precisions:
+            tile, lanes = get_tuning(M, p)
+            rows.append({"M": int(M), "precision": p, "tile": tile, "lanes": lanes})
+    with open(path, "w") as f:
+        json.dump({"librgf": version(), "entries": rows}, f, indent=1)
+
+
+def load_tuning(path: str) -> int:
+    """Apply the entries of a file written by save_tuning; returns how many were applied."""
+    import json
+    with open(path) as f:
+        data = json.load(f)
+    for r in data["entries"]:
+        set_tuning(r["M"], r["precision"], r["tile"], r["lanes"])
+    return len(data["entries"])
 
 
 MIXED_SWEEP, MIXED_LU, MIXED_SOLVE, MIXED_ALL = 1, 2, 4, 7

@@ -56,3 +56,26 @@ def test_argument_errors_before_device_work(lib):
     assert L.rgf_set_tile(0, 96) == rgf.RGF_EINVAL
     assert L.rgf_set_mixed_parts(8) == rgf.RGF_EINVAL
     assert L.rgf_version().startswith(b"librgf")
+
+
+def test_tuning_table_on_the_host(tmp_path):
+    """Set/get of the tuning table and its JSON round trip (no device work)."""
+    from paper_2609_37058_amd import rgf
+    rgf.load()
+    assert rgf.get_tuning(100, "fp64") == (128, 1)      # defaults: 128 tiles, one lane below Mp = 256
+    assert rgf.get_tuning(1024, "mixed") == (128, 2)
+    rgf.set_tuning(100, "fp64", 64, 2)
+    assert rgf.get_tuning(128, "fp64") == (64, 2)       # same padded size class
+    assert rgf.get_tuning(129, "fp64") == (128, 1)
+    path = str(tmp_path / "tune.json")
+    rgf.save_tuning(path, [100, 1024])
+    rgf.set_tuning(100, "fp64", 0, 0)
+    assert rgf.get_tuning(100, "fp64") == (128, 1)
+    assert rgf.load_tuning(path) == 4
+    assert rgf.get_tuning(100, "fp64") == (64, 2)
+    rgf.set_tuning(100, "fp64", 0, 0)
+    L = rgf._lib
+    assert L.rgf_set_tuning(0, 0, 64, 1) == rgf.RGF_EINVAL
+    assert L.rgf_set_tuning(100, 0, 96, 1) == rgf.RGF_EINVAL
+    assert L.rgf_set_tuning(100, 0, 64, 5) == rgf.RGF_EINVAL
+    assert L.rgf_autotune(0, 0, 0, None, None, None) == rgf.RGF_EINVAL

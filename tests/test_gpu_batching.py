@@ -1,0 +1,140 @@
+"""The batching form on the GPU: many devices of uneven size in one call, and the autotuner.
+
+rgf_transmission_batch must give, for every device, exactly (bitwise) what
+rgf_transmission gives for that device alone, and both must meet the FP64
+oracle bar.  The small-block devices share one persistent launch whose
+workgroups draw (device, energy) items from a work counter.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import fp64_close, log, stage
+
+pytestmark = pytest.mark.gpu
+
+
+def _single(lib, dev_t, E, eta, precision="fp64"):
+    import torch
+    T, info = lib.transmission(dev_t, torch.as_tensor(E).cuda(), eta, precision)
+    torch.cuda.synchronize()
+    return T.cpu().numpy(), info.cpu().numpy()
+
+
+def _batch(lib, devs_t, Es, eta, precision="fp64"):
+    import torch
+    res = lib.transmission_batch(devs_t, [torch.as_tensor(E).cuda() for E in Es], eta, precision)
+    torch.cuda.synchronize()
+    return [(T.cpu().numpy(), i.cpu().numpy()) for T, i in res]
+
+
+def _mix(specs, seed):
+    rng = np.random.default_rng(seed)
+    devs, Es = [], []
+    for k, (N, M, nE) in enumerate(specs):
+        devs.append(synth.random_small_device(N, M, seed=seed + 31 * k + M, distinct_leads=bool(k % 2)))
+        Es.append(np.sort(rng.uniform(-2.5, 2.5, nE)))
+    return devs, Es
+
+
+def test_small_devices_share_one_persistent_launch(lib):
+    specs = [(20, 4, 37), (1, 1, 5), (7, 16, 11), (3, 9, 1), (30, 2, 23), (12, 13, 8), (2, 16, 40), (5, 7, 3)]
+    devs, Es = _mix(specs, 900)
+    dts = [stage(d) for d in devs]
+    got = _batch(lib, dts, Es, 1e-6)
+    for (N, M, nE), d, dt, E, (T, info) in zip(specs, devs, dts, Es, got):
+        Ts, infos = _single(lib, dt, E, 1e-6)
+        ref = oracle.transmission(d, E, 1e-6)
+        ok, rel, ab = fp64_close(T, ref)
+        log(f"[batch] small N={N} M={M} nE={nE}: bitwise={np.array_equal(T, Ts)} max rel {rel:.2e}")
+        assert np.array_equal(T, Ts) and np.array_equal(info, infos)
+        assert ok and np.all(info == 0)
+
+
+def test_mixed_sizes_match_single_calls_and_oracle(lib):
+    specs = [(4, 130, 5), (6, 70, 9), (20, 4, 12), (3, 40, 7), (2, 200, 4), (9, 11, 6)]
+    devs, Es = _mix(specs, 1700)
+    dts = [stage(d) for d in devs]
+    got = _batch(lib, dts, Es, 1e-6)
+    for (N, M, nE), d, dt, E, (T, info) in zip(specs, devs, dts, Es, got):
+        Ts, _ = _single(lib, dt, E, 1e-6)
+        ref = oracle.transmission(d, E, 1e-6)
+        ok, rel, ab = fp64_close(T, ref)
+        log(f"[batch] mixed N={N} M={M} nE={nE}: bitwise={np.array_equal(T, Ts)} max rel {rel:.2e}")
+        assert np.array_equal(T, Ts)
+        assert ok and np.all(info == 0)
+
+
+def test_batch_mixed_precision_equals_single_calls(lib):
+    specs = [(3, 70, 4), (2, 130, 3), (5, 8, 5)]
+    devs, Es = _mix(specs, 2500)
+    dts = [stage(d) for d in devs]
+    got = _batch(lib, dts, Es, 1e-6, "mixed")
+    for d, dt, E, (T, info) in zip(devs, dts, Es, got):
+        Ts, _ = _single(lib, dt, E, 1e-6, "mixed")
+        assert np.array_equal(T, Ts)
+        ref = oracle.transmission(d, E, 1e-6)
+        assert np.max(np.abs(T - ref)) <= 1e-4
+
+
+def test_batch_argument_errors(lib):
+    import torch
+    assert lib.load().rgf_transmission_batch(None, -1, None, None, 1e-6, 0, None, None, None) == lib.RGF_EINVAL
+    assert lib.load().rgf_transmission_batch(None, 0, None, None, 1e-6, 0, None, None, None) == lib.RGF_OK
+    d = stage(synth.random_small_device(2, 5, seed=3))
+    with pytest.raises(lib.RgfError):
+        lib.transmission_batch([d], [torch.zeros(2, dtype=torch.float64, device="cuda")], -1.0)
+
+
+def test_autotune_picks_a_measured_choice_and_keeps_results(lib):
+    dev = synth.random_small_device(4, 100, seed=41, distinct_leads=True)
+    dt = stage(dev)
+    E = np.array([-1.3, -0.4, 0.6, 1.7])
+    before, _ = _single(lib, dt, E, 1e-6)
+    try:
+        r = lib.autotune(100, "fp64", batch=16)
+        log(f"[tune] M=100 fp64: tile {r['tile']} lanes {r['lanes']} ms {r['ms']}")
+        assert r["tile"] in (64, 128) and r["lanes"] in (1, 2)
+        assert len(r["ms"]) == 4 and all(v > 0 for v in r["ms"].values())
+        assert r["ms"][(r["tile"], r["lanes"])] == min(r["ms"].values())
+        assert lib.get_tuning(100, "fp64") == (r["tile"], r["lanes"])
+        for tile in (64, 128):
+            lib.set_tuning(100, "fp64", tile, 1)
+            after, _ = _single(lib, dt, E, 1e-6)
+            log(f"[tune] tile {tile}: max |dT| vs default {np.max(np.abs(after - before)):.2e}")
+            assert np.allclose(after, before, rtol=1e-12, atol=1e-14)
+    finally:
+        lib.set_tuning(100, "fp64", 0, 0)
+    assert lib.get_tuning(100, "fp64") == (128, 1)
+
+
+@pytest.mark.parametrize("N,M,nE", [(6, 70, 5), (3, 300, 4)])
+def test_graph_replays_equal_eager_results(lib, N, M, nE):
+    """Captured sweeps: every replay equals the eager path bitwise, with eager work in between.
+
+    M = 300 pads to 320 and splits over two lanes, so each lane captures its own graph.
+    """
+    import torch
+    dev = synth.random_small_device(N, M, seed=60 + M, distinct_leads=True)
+    dt = stage(dev)
+    rng = np.random.default_rng(M)
+    grids = [np.sort(rng.uniform(-2.0, 2.0, nE)) for _ in range(4)]
+    eager = [_single(lib, dt, E, 1e-6)[0] for E in grids]
+    try:
+        lib.set_graphs(True)
+        assert lib.get_graphs()
+        for rep in range(2):
+            for k, E in enumerate(grids):
+                T, info = _single(lib, dt, E, 1e-6)
+                log(f"[graph] N={N} M={M} rep {rep} grid {k}: bitwise={np.array_equal(T, eager[k])}")
+                assert np.array_equal(T, eager[k]) and np.all(info == 0)
+                lib.set_graphs(False)  # eager work between replays
+                Te, _ = _single(lib, dt, grids[(k + 1) % 4], 1e-6)
+                assert np.array_equal(Te, eager[(k + 1) % 4])
+                torch.cuda.synchronize()
+                lib.set_graphs(True)
+        ref = oracle.transmission(dev, grids[0], 1e-6)
+        assert fp64_close(eager[0], ref)[0]
+    finally:
+        lib.set_graphs(False)
