@@ -364,3 +364,43 @@ def random_small_device(N: int, M: int, seed: int, real: bool = False,
     return device_from_blocks([l.H00 for l in layers], [l.H01 for l in layers[:-1]],
                               [l.S00 for l in layers], [l.S01 for l in layers[:-1]],
                               lead, lead_r, name=f"rand{N}x{M}")
+
+
+# ----------------------------------------------------------------------------
+# Transverse lattice images (inputs of k-point sampling)
+# ----------------------------------------------------------------------------
+
+KIND_IMAGE = 5
+
+
+def transverse_images(base: Device, seed: int, scale: float = 0.1, directions=((1, 0), (0, 1))):
+    """Real-space images of a transversely periodic device: (images, R).
+
+    images[0] is ``base`` at R = (0, 0).  For each direction d and the pair
+    +-d, on-site blocks (H_ii, S_ii and the electrodes' H00, S00) get a
+    seeded complex image X(+d) with X(-d) = X(+d)^dagger, so every X(k) is
+    Hermitian; coupling blocks (H_i,i+1, S_i,i+1, H01, S01) get independent
+    seeded images for +d and -d.  H images are ``scale`` x decay-weighted
+    complex N(0,1), S images a tenth of that.  One electrode serves both sides.
+    """
+    N, M = base.N, base.M
+    W = decay_weights(M)
+    dag = lambda x: x.conj().T
+    images, R = [base], [(0, 0)]
+    for j, d in enumerate(directions):
+        rng = lambda layer, kind, sign: _rng(seed, layer, 16 * (KIND_IMAGE + kind) + 4 * j + sign)
+        cn = lambda r, s: s * complex_normal(r, (M, M)) * W
+        hd_p = [cn(rng(i, 0, 0), scale) for i in range(N)]
+        sd_p = [cn(rng(i, 1, 0), 0.1 * scale) for i in range(N)]
+        hu = [[cn(rng(i, 2, sg), scale) for i in range(N - 1)] for sg in (0, 1)]
+        su = [[cn(rng(i, 3, sg), 0.1 * scale) for i in range(N - 1)] for sg in (0, 1)]
+        l00, ls00 = cn(rng(N, 4, 0), scale), cn(rng(N, 5, 0), 0.1 * scale)
+        l01 = [cn(rng(N, 6, sg), scale) for sg in (0, 1)]
+        ls01 = [cn(rng(N, 7, sg), 0.1 * scale) for sg in (0, 1)]
+        plus_lead = Lead(l00, l01[0], ls00, ls01[0])
+        minus_lead = Lead(dag(l00), l01[1], dag(ls00), ls01[1])
+        images.append(device_from_blocks(hd_p, hu[0], sd_p, su[0], plus_lead, plus_lead))
+        images.append(device_from_blocks([dag(x) for x in hd_p], hu[1], [dag(x) for x in sd_p], su[1],
+                                         minus_lead, minus_lead))
+        R += [tuple(d), (-d[0], -d[1])]
+    return images, R
