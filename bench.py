@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="block-product tile (64/128); 0 = library default")
+    ap.add_argument("--workload", choices=["c4", "bias", "kmesh"], default="c4",
+                    help="c4: the headline zero-bias workload; bias: the C4 device at finite bias with the "
+                         "Landauer current; kmesh: a transversely periodic C2-type device on a 7x7 k-mesh")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (read once, written once), three "
                          "times, and exit: the reference kernel that scales the HBM byte counters")
@@ -134,10 +137,100 @@ def measured_traffic():
     return per_energy
 
 
+def _timed_steps(step, steps: int, warmup: int):
+    import torch
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        s0 = time.perf_counter()
+        out = step(warmup + k)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+        print(f"[bench] step {k}: {lat[-1]:.2f} s", file=sys.stderr, flush=True)
+    return time.perf_counter() - t0, lat, out
+
+
+def run_extra_workload(args) -> int:
+    """The finite-bias and the transverse k-mesh forms, each printing one JSON line of its own."""
+    if args.gpus != 1:
+        print("bench.py measures one GPU only", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    import synth
+    from paper_2609_37058_amd import rgf, staging
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    rgf.profile(True)
+    rgf.profile_read()
+    if args.workload == "bias":
+        # the C4 device, symmetric bias V, the window E_F +- (V/2 + 10 kT) on the step's energies
+        cfg = synth.config_c4(n_e=512)
+        d = cfg.device
+        b = d.base
+        dev_t = staging.stage_repeated(b.H00, b.H01, b.S00, b.S01, d.N, d.shifts)
+        EF, V, kT = 0.0, 0.2, 0.0259
+        B = args.energies_per_step
+        half = V / 2 + 10 * kT
+        E = torch.linspace(EF - half, EF + half, B, dtype=torch.float64, device="cuda")
+        step = lambda k: rgf.current(dev_t, E, cfg.eta, EF, V, kT)
+        wall, lat, (T, info, I) = _timed_steps(step, args.steps, args.warmup)
+        units, unit = B * d.N, "energy-point*layers/s"
+        config = {"workload": "c4-bias", "layers": d.N, "block": d.M, "energies_per_step": B,
+                  "bias_V": V, "e_fermi": EF, "kT_eV": kT, "energy_window": [EF - half, EF + half],
+                  "eta": cfg.eta, "precision": "fp64"}
+        extra = {"current_A": float(I.item()), "nonzero_info": int((info != 0).sum().item())}
+    else:
+        # C2-type device (60 random decay-weighted layers, M = 256) with transverse images along
+        # both directions, on the 7x7 mesh of the paper's Pt-Si-Pt transport runs
+        cfg = synth.config_c2(n_layers=60, m=256, n_e=1000)
+        base = cfg.device
+        images, R = synth.transverse_images(base, seed=77)
+        imgs = []
+        for im in images:
+            hd, hu, sd, su = im.stacked()
+            lead = staging.stage_lead(im.left.H00, im.left.H01, im.left.S00, im.left.S01)
+            imgs.append(staging.stage_blocks(hd, hu, sd, su, lead, lead))
+        n1 = 7
+        k1 = (np.arange(n1) + 0.5) / n1 - 0.5
+        kk = np.array([(a, c) for a in k1 for c in k1])
+        w = np.full(len(kk), 1.0 / len(kk))
+        B = min(args.energies_per_step, 16)
+        E = torch.linspace(-1.0, 1.0, B, dtype=torch.float64, device="cuda")
+        step = lambda k: rgf.transmission_kmesh(imgs, R, kk, w, E, cfg.eta)
+        wall, lat, (T, Tk, info) = _timed_steps(step, args.steps, args.warmup)
+        units, unit = B * len(kk) * base.N, "energy-point*k-point*layers/s"
+        config = {"workload": "c2-kmesh", "layers": base.N, "block": base.M, "images": len(R),
+                  "kmesh": [n1, n1], "energies_per_step": B, "eta": cfg.eta, "precision": "fp64"}
+        extra = {"nonzero_info": int((info != 0).sum().item())}
+    n_launch, k_ms, k_flops = rgf.profile_read()
+    rgf.profile(False)
+    achieved = (k_flops / (k_ms / 1e3) / 1e12) if k_ms > 0 else None
+    out = {
+        "metric": f"RGF {unit.split('/')[0]}/s ({args.workload} form)",
+        "value": args.steps * units / wall, "unit": unit, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": config,
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "roofline": {"bound": "mfma", "kernel": "sweep block product (zgemm role 1)", "achieved": achieved,
+                     "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": (achieved / FP64_MFMA_PEAK_TFLOPS) if achieved else None, "traffic": None,
+                     "launches": n_launch, "avg_launch_ms": k_ms / max(1, n_launch)},
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.copy_probe_mib:
         return copy_probe(args.copy_probe_mib)
+    if args.workload != "c4":
+        return run_extra_workload(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (one process, one MI355X); --gpus {args.gpus} is not supported. "
               "The path shards over energies with no exchange during compute; see the design notes.",

@@ -347,14 +347,15 @@ static void sweep_graph(Engine& eng, const rgf_device& d, bool same, int B, int 
 
 // Energies [lo, hi) of one device on one stream, in chunks of at most `chunk`.
 static void run_range(const rgf_device& d, const double* E, int64_t lo, int64_t hi, double eta, int precision,
-                      double* T, int32_t* info, int chunk, hipStream_t ls, double u_l, double u_r) {
+                      double* T, int32_t* info, int chunk, hipStream_t ls, double u_l, double u_r,
+                      const Grouping& grp) {
   const int M = d.M;
   const int Mp = (int)round_up(M, 64);
   // one decimation serves both sides only for the same electrode at the same shift
   const bool same = same_lead(d.left, d.right) && u_l == u_r;
   const bool biased = u_l != 0.0 || u_r != 0.0;
   const int prec = precision == RGF_MIXED ? PREC_F32 : PREC_F64;
-  const bool graphs = graphs_enabled();
+  const bool graphs = graphs_enabled() && grp.per == 0;  // a captured sweep keys on one device
   int dev = 0;
   RGF_HIP(hipGetDevice(&dev));
   for (int64_t e0 = lo; e0 < hi;) {
@@ -368,6 +369,7 @@ static void run_range(const rgf_device& d, const double* E, int64_t lo, int64_t 
       Ec = Ew;
     }
     Engine eng(w.base, lay, ls, prec, M, Ec, eta, w.host_active);
+    if (grp.per > 0) eng.set_group(grp.per, e0, grp.stride);
     if (biased) {  // a rigidly shifted electrode is the unshifted one at E - u
       double* El = reinterpret_cast<double*>(w.base + lay.elead);
       double* Er = reinterpret_cast<double*>(w.base + lay.erlead);
@@ -393,9 +395,10 @@ static void run_range(const rgf_device& d, const double* E, int64_t lo, int64_t 
 }
 
 void run_device(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
-                int32_t* info, hipStream_t st, double mem_share, double u_l, double u_r) {
+                int32_t* info, hipStream_t st, double mem_share, double u_l, double u_r, const Grouping& grp) {
   if (nE <= 0) return;
   if (uses_small_path(d.M, precision)) {
+    RGF_CHECK(grp.per == 0, RGF_EINVAL, "grouped batches need the batched path");
     SmallArgs a = small_args(d, E, nE, eta, T, info);
     a.u_l = u_l;
     a.u_r = u_r;
@@ -403,13 +406,13 @@ void run_device(const rgf_device& d, const double* E, int64_t nE, double eta, in
     return;
   }
   const int Mp = (int)round_up(d.M, 64);
-  run_range(d, E, 0, nE, eta, precision, T, info, chunk_for(Mp, nE, mem_share), st, u_l, u_r);
+  run_range(d, E, 0, nE, eta, precision, T, info, chunk_for(Mp, nE, mem_share), st, u_l, u_r, grp);
 }
 
 // One device, energies [0, nE): small-block fused kernel or the batched path,
 // the latter split over the energy lanes.
 void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
-                       int32_t* info, hipStream_t st, double u_l, double u_r) {
+                       int32_t* info, hipStream_t st, double u_l, double u_r, const Grouping& grp) {
   const int Mp = (int)round_up(d.M, 64);
   const int prec = precision == RGF_MIXED ? PREC_F32 : PREC_F64;
   const bool small = uses_small_path(d.M, precision);
@@ -418,7 +421,7 @@ void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double 
   // caller's stream when that is the legacy default stream), so one lane then
   // also goes through the lane path.
   if (small || (nl == 1 && !graphs_enabled())) {
-    run_device(d, E, nE, eta, precision, T, info, st, 1.0, u_l, u_r);
+    run_device(d, E, nE, eta, precision, T, info, st, 1.0, u_l, u_r, grp);
     return;
   }
   int dev = 0;
@@ -441,7 +444,7 @@ void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double 
       try {
         RGF_HIP(hipSetDevice(dev));
         RGF_HIP(hipStreamWaitEvent(lanes[i].st, lanes[0].fork, 0));
-        run_range(d, E, lo, hi, eta, precision, T, info, lane_chunk, lanes[i].st, u_l, u_r);
+        run_range(d, E, lo, hi, eta, precision, T, info, lane_chunk, lanes[i].st, u_l, u_r, grp);
         RGF_HIP(hipEventRecord(lanes[i].done, lanes[i].st));
       } catch (const Error& e) {
         errs[i] = e;

@@ -66,17 +66,29 @@ struct MatRef {
 // on the diagonal when pad_identity is set).  conj_t forms (z_b*S - H)
 // with S, H replaced by their adjoints: z_b*S^+ - H^+.
 // z_b = E[b] + i*eta.  When sub is set, sub_sign*sub[b] is added.
+// Grouped batches (gper > 0): batch entry b reads the blocks of group
+// (gb0 + b) / gper, which sit gstride elements after those of the group
+// before (several devices of one shape, e.g. the k-points of a mesh, in one
+// batch).
 struct FormRef {
   const z64* H;
   const z64* S;
   int32_t M;
   int32_t conj_t;
   int32_t pad_identity;
+  int32_t gper;
+  int64_t gb0;
+  int64_t gstride;
   const double* E;
   double eta;
   MatRef sub;        // optional per-batch matrix added with sub_sign (p == nullptr: none)
   double sub_sign;
 };
+
+// element offset of batch entry b's blocks in a grouped batch
+__host__ __device__ inline int64_t form_group_off(const FormRef& f, int b) {
+  return f.gper > 0 ? ((f.gb0 + b) / f.gper) * f.gstride : 0;
+}
 
 // Per-batch skip flags: a batch entry with skip[b] != 0 is left untouched.
 struct BatchCtl {
@@ -87,12 +99,13 @@ __device__ inline z64 form_elem(const FormRef& f, int b, int r, int c) {
   z64 v = zmake(0.0, 0.0);
   if (r < f.M && c < f.M) {
     z64 z = zmake(f.E[b], f.eta);
+    const int64_t g = form_group_off(f, b);
     if (f.conj_t) {
-      z64 s = f.S[(int64_t)c * f.M + r];
-      z64 h = f.H[(int64_t)c * f.M + r];
+      z64 s = f.S[g + (int64_t)c * f.M + r];
+      z64 h = f.H[g + (int64_t)c * f.M + r];
       v = zform(z, zconj(s), zconj(h));
     } else {
-      v = zform(z, f.S[(int64_t)r * f.M + c], f.H[(int64_t)r * f.M + c]);
+      v = zform(z, f.S[g + (int64_t)r * f.M + c], f.H[g + (int64_t)r * f.M + c]);
     }
   } else if (f.pad_identity && r == c) {
     v = zmake(1.0, 0.0);
@@ -128,6 +141,9 @@ inline FormRef form(const rgf_z* H, const rgf_z* S, int M, bool conj_t, bool pad
   f.M = M;
   f.conj_t = conj_t ? 1 : 0;
   f.pad_identity = pad_identity ? 1 : 0;
+  f.gper = 0;
+  f.gb0 = 0;
+  f.gstride = 0;
   f.E = E;
   f.eta = eta;
   f.sub = nomat();

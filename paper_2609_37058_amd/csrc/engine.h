@@ -48,6 +48,14 @@ class Engine {
     EL_ = EL;
     ER_ = ER;
   }
+  // A grouped batch: entry b uses the device and electrode blocks of group
+  // (b0 + b) / per, `stride` elements after those of the group before; the
+  // blocks passed to the calls below are those of group 0.
+  void set_group(int per, int64_t b0, int64_t stride) {
+    gper_ = per;
+    gb0_ = b0;
+    gstride_ = stride;
+  }
   // decimation of `lead` for all energies of the chunk (those of side `left`);
   // leaves eps_L, eps_R
   void decimate(const rgf_lead& lead, int32_t* done, bool left = true);
@@ -73,12 +81,20 @@ class Engine {
   MatRef mref(z64* p, int64_t ld, int64_t bstride, const int32_t* ridx = nullptr) const;
   FillArgs fill_args(MatRef dst, int rows, int cols, int kind) const;
   double gemm(GemmArgs g, int prec, bool timed);
+  FormRef gform(FormRef f) const {
+    f.gper = gper_;
+    f.gb0 = gb0_;
+    f.gstride = gstride_;
+    return f;
+  }
 
   hipStream_t st_;
   int prec_, M_, Mp_, B_;
   const double* E_;
   const double *EL_, *ER_;  // lead energies per side (E_ unless shifted)
   double eta_;
+  int gper_ = 0;
+  int64_t gb0_ = 0, gstride_ = 0;
   int64_t MM_;
   int nblk_sr_;
   z64 *sigL_, *sigR_, *gamL_, *gamR_;
@@ -90,6 +106,14 @@ class Engine {
   int32_t* host_active_;
 };
 
+// Several devices of one shape in one batch: group g's blocks (device and
+// electrodes) sit g * stride elements after those of the device passed, and
+// its `per` energies are entries [g * per, (g + 1) * per) of the batch.
+struct Grouping {
+  int per = 0;  // 0: one device
+  int64_t stride = 0;
+};
+
 // ---- one device through the path (api.hip) ----
 void check_device(const rgf_device& d);
 bool uses_small_path(int M, int precision);
@@ -98,8 +122,10 @@ SmallArgs small_args(const rgf_device& d, const double* E, int64_t nE, double et
 // workspace budget when several devices run side by side
 // u_l, u_r: rigid shifts of the left / right electrode (finite bias; 0 at zero bias)
 void run_device(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
-                int32_t* info, hipStream_t st, double mem_share, double u_l = 0.0, double u_r = 0.0);
+                int32_t* info, hipStream_t st, double mem_share, double u_l = 0.0, double u_r = 0.0,
+                const Grouping& grp = Grouping());
 void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
-                       int32_t* info, hipStream_t st, double u_l = 0.0, double u_r = 0.0);
+                       int32_t* info, hipStream_t st, double u_l = 0.0, double u_r = 0.0,
+                       const Grouping& grp = Grouping());
 
 }  // namespace rgf

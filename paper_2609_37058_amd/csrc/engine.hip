@@ -174,7 +174,7 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
   RGF_HIP(hipMemsetAsync(iters_, 0, sizeof(int32_t) * B_, st_));
   // eps = eps_L = eps_R = D (identity padding), alpha = U, beta = L
   FillArgs f = fill_args(mref(eps_, Mp, MM_), Mp, Mp, FILL_FORM);
-  f.f = form(lead.H00, lead.S00, M_, false, true, El, eta_);
+  f.f = gform(form(lead.H00, lead.S00, M_, false, true, El, eta_));
   launch_fill(f, B_, st_);
   f = fill_args(mref(epsL_, Mp, MM_), Mp, Mp, FILL_MAT);
   f.src = mref(eps_, Mp, MM_);
@@ -182,7 +182,7 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
   f.dst = mref(epsR_, Mp, MM_);
   launch_fill(f, B_, st_);
   f = fill_args(mref(AB_, Mp, 2 * MM_), Mp, Mp, FILL_FORM);
-  f.f = form(lead.H01, lead.S01, M_, false, false, El, eta_);
+  f.f = gform(form(lead.H01, lead.S01, M_, false, false, El, eta_));
   launch_fill(f, B_, st_);
   f.dst = mref(AB_ + MM_, Mp, 2 * MM_);
   f.f.conj_t = 1;
@@ -242,14 +242,14 @@ void Engine::self_energy(const rgf_lead& lead, bool left, z64* out) {
   // RHS: U of the lead (left side) or L (right side), rows gathered by the pivots
   f = fill_args(mref(Ysr_, Mp, 2 * MM_), Mp, Mp, FILL_FORM);
   const double* El = left ? EL_ : ER_;
-  f.f = form(lead.H01, lead.S01, M_, /*conj_t=*/!left, false, El, eta_);
+  f.f = gform(form(lead.H01, lead.S01, M_, /*conj_t=*/!left, false, El, eta_));
   f.ridx = lu_.perm;
   f.ridx_bs = Mp;
   launch_fill(f, B_, st_);
   lu_solve(lu_, Tsr_, MM_, Mp, Ysr_, 2 * MM_, Mp, B_, nullptr, PREC_F64, tile, st_);
   GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
   g.a_kind = SRC_FORM;
-  g.Af = form(lead.H01, lead.S01, M_, /*conj_t=*/left, false, El, eta_);
+  g.Af = gform(form(lead.H01, lead.S01, M_, /*conj_t=*/left, false, El, eta_));
   g.B = mref(Ysr_, Mp, 2 * MM_);
   g.C = mref(out, Mp, MM_);
   gemm(g, PREC_F64, false);
@@ -275,7 +275,7 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
 
   // B_0 = A_00 - Sigma_L (- Sigma_R when N = 1)
   FillArgs f = fill_args(mref(T_, Mp, MM_), Mp, Mp, FILL_FORM);
-  f.f = form(d.Hd, d.Sd, M_, false, true, E_, eta_);
+  f.f = gform(form(d.Hd, d.Sd, M_, false, true, E_, eta_));
   f.f.sub = mref(sigL_, Mp, MM_);
   f.f.sub_sign = -1.0;
   launch_fill(f, B_, st_);
@@ -290,7 +290,7 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
     // X = B_l^-1 U_l
     lu_factor(lu_, T_, MM_, Mp, B_, nullptr, l + 1, lp, tile, st_);
     f = fill_args(mref(Y_, Mp, MM_), Mp, Mp, FILL_FORM);
-    f.f = form(d.Hu + l * M2, d.Su + l * M2, M_, false, false, E_, eta_);
+    f.f = gform(form(d.Hu + l * M2, d.Su + l * M2, M_, false, false, E_, eta_));
     f.ridx = lu_.perm;
     f.ridx_bs = Mp;
     launch_fill(f, B_, st_);
@@ -311,10 +311,10 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
     // B_{l+1} = A_{l+1} - L_{l+1} X (- Sigma_R on the last layer)
     GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
     g.a_kind = SRC_FORM;
-    g.Af = form(d.Hu + l * M2, d.Su + l * M2, M_, true, false, E_, eta_);
+    g.Af = gform(form(d.Hu + l * M2, d.Su + l * M2, M_, true, false, E_, eta_));
     g.B = X;
     g.c_kind = SRC_FORM;
-    g.Cf = form(d.Hd + (l + 1) * M2, d.Sd + (l + 1) * M2, M_, false, true, E_, eta_);
+    g.Cf = gform(form(d.Hd + (l + 1) * M2, d.Sd + (l + 1) * M2, M_, false, true, E_, eta_));
     if (l + 2 == N) {
       g.Cf.sub = mref(sigR_, Mp, MM_);
       g.Cf.sub_sign = -1.0;

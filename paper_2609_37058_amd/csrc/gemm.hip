@@ -64,12 +64,15 @@ struct CT<float> {
   __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-// Element (r, c) of the Cin operand of batch entry b (a matrix or a formed block).
-__device__ inline z64 c_value(const GemmArgs& g, int b, int r, int c, z64 zc) {
+// Element (r, c) of the Cin operand of batch entry b (a matrix or a formed
+// block whose blocks start coff elements after Cf's: a grouped batch).
+__device__ inline z64 c_value(const GemmArgs& g, int b, int r, int c, z64 zc, int64_t coff) {
   if (g.c_kind == SRC_MAT) return g.Cin.p[mat_off(g.Cin, b, r, c)];
   z64 f = zmake(0.0, 0.0);
-  if (r < g.Cf.M && c < g.Cf.M)
-    f = zform(zc, g.Cf.S[(int64_t)r * g.Cf.M + c], g.Cf.H[(int64_t)r * g.Cf.M + c]);
+  if (r < g.Cf.M && c < g.Cf.M) {
+    const int64_t o = coff + (int64_t)r * g.Cf.M + c;
+    f = zform(zc, g.Cf.S[o], g.Cf.H[o]);
+  }
   else if (g.Cf.pad_identity && r == c)
     f = zmake(1.0, 0.0);
   if (g.Cf.sub.p) {
@@ -139,8 +142,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int t
   z64 zz = zmake(0.0, 0.0);
   if constexpr (FORM) {
     a_M = g.Af.M;
-    a_s = g.Af.S;
-    a_h = g.Af.H;
+    a_s = g.Af.S + form_group_off(g.Af, b);
+    a_h = g.Af.H + form_group_off(g.Af, b);
     zz = zmake(g.Af.E[b], g.Af.eta);
   } else {
     a_ptr = g.A.p + mat_off(g.A, b, a_ok ? row0 + a_r : 0, a_k);
@@ -213,6 +216,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int t
   // FP64 with alpha = +-1: the accumulators start at Cin / alpha, so the Cin
   // loads overlap the first stage's loads instead of stalling the epilogue
   const bool c_pre = CT<R>::exact && g.c_kind != SRC_NONE && (g.alpha == 1.0 || g.alpha == -1.0);
+  const int64_t c_off = form_group_off(g.Cf, b);
   if (c_pre && w_active) {
     const z64 zc = (g.c_kind == SRC_FORM) ? zmake(g.Cf.E[b], g.Cf.eta) : zmake(0.0, 0.0);
 #pragma unroll
@@ -223,7 +227,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int t
         for (int v = 0; v < 4; ++v) {
           const int r = row0 + wm * WTM + i * 16 + CT<R>::out_row(lane, v);
           const int c = col0 + wn * WTN + j * 16 + (lane & 15);
-          const z64 cin = c_value(g, b, r, c, zc);
+          const z64 cin = c_value(g, b, r, c, zc, c_off);
           accr[i][j][v] = (R)(g.alpha * cin.x);
           acci[i][j][v] = (R)(g.alpha * cin.y);
         }
@@ -278,7 +282,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int t
         const int r = row0 + wm * WTM + i * 16 + CT<R>::out_row(lane, v);
         const int c = col0 + wn * WTN + j * 16 + (lane & 15);
         z64 out = zmake(g.alpha * (double)accr[i][j][v], g.alpha * (double)acci[i][j][v]);
-        if (!c_pre && g.c_kind != SRC_NONE) out = zadd(out, c_value(g, b, r, c, zc));
+        if (!c_pre && g.c_kind != SRC_NONE) out = zadd(out, c_value(g, b, r, c, zc, c_off));
         g.C.p[mat_off(g.C, b, r, c)] = out;
       }
 }

@@ -3,9 +3,13 @@
 // k-point meshes (the per-stage cost is per energy and per transverse
 // k-point).  Every block is given for a set of transverse lattice images R;
 // at the fractional wavevector k each block is X(k) = sum_R X(R)
-// exp(2 pi i k.R) (one HBM-bound Bloch-sum kernel per block array), the
-// k-resolved transmissions of a group of k-points run as one multi-device
-// batch, and T(E) = sum_k w_k T_k(E) is accumulated in mesh order.
+// exp(2 pi i k.R) (one HBM-bound Bloch-sum kernel per block array).  The
+// assembled devices of a group of k-points sit at one stride in memory and
+// all have the shape (N, M), so their energies run as one grouped batch of
+// the batched path (k-points x energies fill the chip even at a few
+// energies); blocks small enough for the fused small-block kernel go through
+// the multi-device batch instead.  T(E) = sum_k w_k T_k(E) is accumulated in
+// mesh order.
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -70,7 +74,7 @@ extern "C" int rgf_transmission_kmesh(const rgf_device* images, int32_t nR, cons
     const int64_t per_k = 2 * nd + 2 * nu + (shared_leads ? 4 : 8) * MM;  // complex elements
     size_t fr = 0, tot = 0;
     RGF_HIP(hipMemGetInfo(&fr, &tot));
-    const size_t per_k_bytes = sizeof(z64) * per_k + (sizeof(double) + sizeof(int32_t)) * nE + 1024;
+    const size_t per_k_bytes = sizeof(z64) * per_k + (2 * sizeof(double) + sizeof(int32_t)) * nE + 1024;
     int G = (int)std::max<int64_t>(1, std::min<int64_t>(nk, (int64_t)(0.2 * (double)fr / (double)per_k_bytes)));
     G = std::min(G, 64);
     const size_t need = (size_t)G * per_k_bytes + (Tk ? 0 : sizeof(double) * nE * nk) + 4096;
@@ -94,7 +98,15 @@ extern "C" int rgf_transmission_kmesh(const rgf_device* images, int32_t nR, cons
     };
     std::vector<z64*> slots(G);
     for (int g = 0; g < G; ++g) slots[g] = reinterpret_cast<z64*>(take(sizeof(z64) * per_k));
+    const int64_t stride = round_up((int64_t)sizeof(z64) * per_k, 256) / (int64_t)sizeof(z64);
     double* Tk_rows = Tk ? Tk : reinterpret_cast<double*>(take(sizeof(double) * nE * nk));
+    const bool grouped = !uses_small_path(M, precision) && nE <= (1 << 30);
+    double* Eall = nullptr;  // the energies once per k-point of a group
+    if (grouped) {
+      Eall = reinterpret_cast<double*>(take(sizeof(double) * nE * G));
+      for (int g = 0; g < G; ++g)
+        RGF_HIP(hipMemcpyAsync(Eall + (int64_t)g * nE, E, sizeof(double) * nE, hipMemcpyDeviceToDevice, st));
+    }
 
     for (int k0 = 0; k0 < nk; k0 += G) {
       const int gn = std::min(G, nk - k0);
@@ -149,8 +161,16 @@ extern "C" int rgf_transmission_kmesh(const rgf_device* images, int32_t nR, cons
         Ts[g] = Tk_rows + (int64_t)k * nE;
         Is[g] = info ? info + (int64_t)k * nE : nullptr;
       }
-      transmission_batch_impl(kdev.data(), gn, Es.data(), counts.data(), eta, precision, Ts.data(),
-                              info ? Is.data() : nullptr, st);
+      if (grouped) {
+        Grouping grp;
+        grp.per = (int)nE;
+        grp.stride = stride;
+        transmission_impl(kdev[0], Eall, (int64_t)gn * nE, eta, precision, Ts[0], info ? Is[0] : nullptr, st,
+                          0.0, 0.0, grp);
+      } else {
+        transmission_batch_impl(kdev.data(), gn, Es.data(), counts.data(), eta, precision, Ts.data(),
+                                info ? Is.data() : nullptr, st);
+      }
       for (int g = 0; g < gn; ++g) launch_kaccum(T, Tk_rows + (int64_t)(k0 + g) * nE, weights[k0 + g], nE, k0 + g == 0, st);
     }
     RGF_HIP(hipEventRecord(ka.done, st));

@@ -1,9 +1,10 @@
 """Transverse k-point sampling on the GPU against the FP64 oracle.
 
 Blocks are given for transverse lattice images; the library forms X(k) with
-a Bloch-sum kernel, runs the k-resolved transmissions as one multi-device
-batch and averages them with the mesh weights.  FP64 bar element by element
-on every T_k and on the average.
+a Bloch-sum kernel, runs the k-resolved transmissions of all k-points as one
+grouped batch (the fused small-block kernel's multi-device batch for tiny
+blocks) and averages them with the mesh weights.  FP64 bar element by
+element on every T_k and on the average.
 """
 import numpy as np
 import pytest
@@ -29,8 +30,8 @@ def _images(N, M, seed, distinct=False):
     lead_p, lead_m = synth.Lead(*lp), synth.Lead(*lm)
     plus = synth.device_from_blocks(list(hd), list(hu_p), list(sd), list(su_p), lead_p, lead_p)
     minus = synth.device_from_blocks(list(dag(hd)), list(hu_m), list(dag(sd)), list(su_m), lead_m, lead_m)
-    if distinct:  # distinct electrodes in the R = 0 image only; the +-R images keep equal ones
-        pass
+    # with distinct=True only the R = 0 image has two different electrodes, which is
+    # enough to make every k-point's left and right electrode differ
     return [d0, plus, minus], [[0, 0], [1, 0], [-1, 0]]
 
 
@@ -38,10 +39,11 @@ def _stage_images(images):
     return [stage(im) for im in images]
 
 
-@pytest.mark.parametrize("N,M", [(4, 3), (3, 16), (3, 40), (2, 70)])
-def test_kmesh_matches_oracle(lib, N, M):
+@pytest.mark.parametrize("N,M,distinct", [(4, 3, False), (3, 16, False), (3, 40, False), (2, 70, False),
+                                          (3, 16, True), (3, 40, True)])
+def test_kmesh_matches_oracle(lib, N, M, distinct):
     import torch
-    images, R = _images(N, M, seed=500 + M)
+    images, R = _images(N, M, seed=500 + M, distinct=distinct)
     kk, w = oracle.monkhorst_pack(3, 2)
     E = np.array([-1.2, -0.3, 0.5, 1.4])
     T, Tk, info = lib.transmission_kmesh(_stage_images(images), R, kk, w, torch.as_tensor(E).cuda(), 1e-6)
@@ -49,8 +51,26 @@ def test_kmesh_matches_oracle(lib, N, M):
     T_ref, Tk_ref = oracle.transmission_kmesh(images, R, kk, w, E, 1e-6)
     ok_k, rel_k, _ = fp64_close(Tk.cpu().numpy().ravel(), Tk_ref.ravel())
     ok, rel, _ = fp64_close(T.cpu().numpy(), T_ref)
-    log(f"[kmesh] N={N} M={M} nk={len(kk)}: T_k max rel {rel_k:.2e}, T max rel {rel:.2e}")
+    log(f"[kmesh] N={N} M={M} distinct={distinct} nk={len(kk)}: T_k max rel {rel_k:.2e}, T max rel {rel:.2e}")
     assert ok_k and ok and np.all(info.cpu().numpy() == 0)
+
+
+def test_kmesh_chunks_across_k_points_are_bitwise_equal(lib, monkeypatch):
+    """Energy chunks and lanes that start inside a k-point's energies give the same bits."""
+    import torch
+    images, R = _images(3, 40, seed=611)
+    kk, w = oracle.monkhorst_pack(3, 3)
+    E = torch.as_tensor(np.linspace(-1.0, 1.0, 5)).cuda()
+    staged = _stage_images(images)
+    T0, Tk0, i0 = lib.transmission_kmesh(staged, R, kk, w, E, 1e-6)
+    torch.cuda.synchronize()
+    for chunk, lanes in (("3", "1"), ("7", "2"), ("2", "3")):
+        monkeypatch.setenv("RGF_MAX_CHUNK", chunk)
+        monkeypatch.setenv("RGF_LANES", lanes)
+        T1, Tk1, i1 = lib.transmission_kmesh(staged, R, kk, w, E, 1e-6)
+        torch.cuda.synchronize()
+        log(f"[kmesh] chunk {chunk} lanes {lanes}: equal {torch.equal(Tk0, Tk1)}")
+        assert torch.equal(Tk0, Tk1) and torch.equal(T0, T1) and torch.equal(i0, i1)
 
 
 def test_single_image_equals_plain_transmission(lib):
