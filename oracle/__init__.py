@@ -34,3 +34,9 @@ from .kmesh import (  # noqa: F401
     transmission_kmesh,
     monkhorst_pack,
 )
+from .ldos import (  # noqa: F401
+    local_dos,
+    ldos_dense,
+    ldos_layers,
+    device_matrix,
+)
