@@ -41,9 +41,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="block-product tile (64/128); 0 = library default")
-    ap.add_argument("--workload", choices=["c4", "bias", "kmesh"], default="c4",
+    ap.add_argument("--workload", choices=["c4", "bias", "kmesh", "ldos"], default="c4",
                     help="c4: the headline zero-bias workload; bias: the C4 device at finite bias with the "
-                         "Landauer current; kmesh: a transversely periodic C2-type device on a 7x7 k-mesh")
+                         "Landauer current; kmesh: a transversely periodic C2-type device on a 7x7 k-mesh; "
+                         "ldos: orbital-resolved LDOS and both injected parts of the C3 device")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (read once, written once), three "
                          "times, and exit: the reference kernel that scales the HBM byte counters")
@@ -183,6 +184,21 @@ def run_extra_workload(args) -> int:
                   "bias_V": V, "e_fermi": EF, "kT_eV": kT, "energy_window": [EF - half, EF + half],
                   "eta": cfg.eta, "precision": "fp64"}
         extra = {"current_A": float(I.item()), "nonzero_info": int((info != 0).sum().item())}
+    elif args.workload == "ldos":
+        # the C3 device (200 layers, M = 512, 5% doped), LDOS and both injected parts per energy
+        cfg = synth.config_c3()
+        d = cfg.device
+        b = d.base
+        dev_t = staging.stage_repeated(b.H00, b.H01, b.S00, b.S01, d.N, d.shifts)
+        B = min(args.energies_per_step, 32)
+        E = torch.linspace(-0.5, 0.5, B, dtype=torch.float64, device="cuda")
+        step = lambda k: rgf.ldos(dev_t, E, cfg.eta)
+        wall, lat, (dos, adl, adr, info) = _timed_steps(step, args.steps, args.warmup)
+        units, unit = B * d.N, "energy-point*layers/s"
+        config = {"workload": "c3-ldos", "layers": d.N, "block": d.M, "energies_per_step": B,
+                  "outputs": ["dos", "ados_left", "ados_right"], "eta": cfg.eta, "precision": "fp64"}
+        extra = {"nonzero_info": int((info != 0).sum().item()),
+                 "sum_rule_max_rel": float(((dos - adl - adr).abs().max() / dos.abs().max()).item())}
     else:
         # C2-type device (60 random decay-weighted layers, M = 256) with transverse images along
         # both directions, on the 7x7 mesh of the paper's Pt-Si-Pt transport runs
@@ -215,7 +231,8 @@ def run_extra_workload(args) -> int:
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": config,
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "roofline": {"bound": "mfma", "kernel": "sweep block product (zgemm role 1)", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": ("LDOS block products" if args.workload == "ldos" else
+                                                 "sweep block product") + " (zgemm role 1)", "achieved": achieved,
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / FP64_MFMA_PEAK_TFLOPS) if achieved else None, "traffic": None,
                      "launches": n_launch, "avg_launch_ms": k_ms / max(1, n_launch)},

@@ -175,13 +175,34 @@ int rgf_landauer_current(const double* E, const double* T, int64_t nE, double mu
  * Outputs (DEVICE pointers): T[nE]; Tk[nk][nE] (may be NULL); info[nk][nE]
  * (may be NULL).  Electrodes whose blocks are pointer-equal in every image
  * share one decimation.  The assembled devices of up to 64 k-points at a
- * time (within 20% of free memory) run as one rgf_transmission_batch.
+ * time (within 20% of free memory) run as one batch of k-points x energies
+ * (blocks with M <= 16: one multi-device rgf_transmission_batch).
  * Stream-ordered; RGF_EINVAL for nR outside [1, 32], nk < 1, images of
  * different N or M, or no image with electrode blocks.
  */
 int rgf_transmission_kmesh(const rgf_device* images, int32_t nR, const int32_t* R, const double* kpts,
                            const double* weights, int32_t nk, const double* E, int64_t nE, double eta,
                            int precision, double* T, double* Tk, int32_t* info, void* stream);
+
+/*
+ * rgf_ldos -- orbital-resolved local density of states of the device (paper:
+ * Discussion, the spatially resolved LDOS at zero and finite bias; textbook
+ * NEGF definitions with the Mulliken projection inside the device).  With
+ * G = (z S - H - Sigma_L (+) Sigma_R)^-1, z = E + i eta, on the device:
+ *   dos[e][l][mu]        = (1/2pi) Re [A S]_mu,mu,   A = i (G - G^+)
+ *   ados_left[e][l][mu]  = (1/2pi) Re [A_L S]_mu,mu, A_L = G Gamma_L G^+
+ *   ados_right[e][l][mu] = (1/2pi) Re [A_R S]_mu,mu, A_R = G Gamma_R G^+
+ * for layer l and orbital mu (S the device overlap; device-electrode overlap
+ * terms are not part of the projection).  dos = ados_left + ados_right +
+ * (eta/pi) Re diag(G S G^+ S).  Arrays are [nE][N][M] doubles, DEVICE
+ * pointers, row-major; any of the three may be NULL (not all).  info[nE]
+ * (DEVICE, may be NULL) as in rgf_transmission.  FP64 only.  The library keeps
+ * N padded M x M blocks per energy in its workspace (N Mp^2 x 16 bytes, Mp =
+ * M rounded up to 64), so energies run in chunks that fit 80% of free HBM.
+ * Stream-ordered; RGF_EINVAL as rgf_transmission and when no output is given.
+ */
+int rgf_ldos(const rgf_device* dev, const double* E, int64_t nE, double eta, double* dos, double* ados_left,
+             double* ados_right, int32_t* info, void* stream);
 
 /*
  * lead_self_energy -- Sigma of one lead for side RGF_LEFT (L g_L U) or

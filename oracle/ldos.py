@@ -106,7 +106,7 @@ class _BlockThomas:
         N, M = self.N, self.M
         y = [np.zeros((M, M), np.complex128) for _ in range(N)]
         y[q] = np.eye(M, dtype=np.complex128)
-        for i in range(1, N):  # forward elimination of the right-hand side
+        for i in range(q + 1, N):  # forward elimination of the right-hand side (zero above row q)
             y[i] = y[i] - self.lo[i - 1] @ sla.lu_solve(self.lus[i - 1], y[i - 1])
         x = [None] * N
         x[N - 1] = sla.lu_solve(self.lus[N - 1], y[N - 1])

@@ -565,6 +565,44 @@ void transmission_batch_impl(const rgf_device* devs, int ndev, const double* con
   }
 }
 
+// LDOS: the chunk keeps N padded blocks per energy besides the usual
+// workspace, so it is sized from the whole per-energy footprint.
+void ldos_impl(const rgf_device& d, const double* E, int64_t nE, double eta, double* dos, double* ados_l,
+               double* ados_r, int32_t* info, hipStream_t st) {
+  const int M = d.M, N = d.N;
+  const int Mp = (int)round_up(M, 64);
+  const int64_t MM = (int64_t)Mp * Mp;
+  const bool same = same_lead(d.left, d.right);
+  int dev = 0;
+  RGF_HIP(hipGetDevice(&dev));
+  size_t fr = 0, tot = 0;
+  RGF_HIP(hipMemGetInfo(&fr, &tot));
+  double frac = 0.80;
+  if (const char* s = std::getenv("RGF_MEM_FRACTION")) frac = std::atof(s);
+  const size_t per = Layout::make(Mp, 1).bytes + sizeof(z64) * (size_t)(N * MM) + 2 * sizeof(double) + 512;
+  int64_t chunk = std::max<int64_t>(1, (int64_t)(frac * (double)fr / (double)per));
+  if (const char* s = std::getenv("RGF_MAX_CHUNK")) chunk = std::min<int64_t>(chunk, std::max(1, std::atoi(s)));
+  chunk = std::min<int64_t>(std::min<int64_t>(chunk, nE), 65535);
+  const int64_t out_per = (int64_t)N * M;
+  for (int64_t e0 = 0; e0 < nE;) {
+    const int B = (int)std::min<int64_t>(chunk, nE - e0);
+    const Layout lay = Layout::make(Mp, B);
+    const size_t store_off = round_up((int64_t)lay.bytes, 256);
+    const size_t twos_off = store_off + round_up((int64_t)(sizeof(z64) * (size_t)B * N * MM), 256);
+    Workspace& w = workspace(dev, st, twos_off + sizeof(double) * B);
+    Engine eng(w.base, lay, st, PREC_F64, M, E + e0, eta, w.host_active);
+    eng.decimate(d.left, eng.done_l(), true);
+    eng.self_energy(d.left, true, eng.sigL());
+    if (!same) eng.decimate(d.right, eng.done_r(), false);
+    eng.self_energy(d.right, false, eng.sigR());
+    eng.broadenings();
+    eng.local_dos(d, reinterpret_cast<z64*>(w.base + store_off), reinterpret_cast<double*>(w.base + twos_off),
+                  dos ? dos + e0 * out_per : nullptr, ados_l ? ados_l + e0 * out_per : nullptr,
+                  ados_r ? ados_r + e0 * out_per : nullptr, info ? info + e0 : nullptr, same);
+    e0 += B;
+  }
+}
+
 void self_energy_impl(const rgf_lead& lead, int side, const double* E, int64_t nE, double eta, int precision,
                       rgf_z* sigma, int32_t* info, hipStream_t st) {
   (void)precision;  // decimation and self-energies always run in FP64
@@ -629,6 +667,18 @@ int rgf_transmission_bias(const rgf_device* dev, const double* E, int64_t nE, do
     RGF_CHECK(std::isfinite(u_left) && std::isfinite(u_right), RGF_EINVAL, "electrode shifts must be finite");
     if (nE == 0) return;
     transmission_impl(*dev, E, nE, eta, precision, T, info, (hipStream_t)stream, u_left, u_right);
+  });
+}
+
+int rgf_ldos(const rgf_device* dev, const double* E, int64_t nE, double eta, double* dos, double* ados_left,
+             double* ados_right, int32_t* info, void* stream) {
+  return guarded([&] {
+    RGF_CHECK(dev, RGF_EINVAL, "null device");
+    check_device(*dev);
+    RGF_CHECK(dos || ados_left || ados_right, RGF_EINVAL, "no output requested");
+    check_common(E, nE, eta, RGF_FP64, dos ? dos : (ados_left ? ados_left : ados_right));
+    if (nE == 0) return;
+    ldos_impl(*dev, E, nE, eta, dos, ados_left, ados_right, info, (hipStream_t)stream);
   });
 }
 

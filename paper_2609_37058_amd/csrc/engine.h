@@ -65,6 +65,11 @@ class Engine {
   void broadenings();
   // recursive sweep over the device, then the Caroli trace into T/info
   void sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool same_leads);
+  // orbital-resolved LDOS and the electrode-injected parts, each [batch][N][M]
+  // (any may be null), after the self-energies and broadenings; `store` holds
+  // N Mp^2 per energy (batch stride N Mp^2), `twos` one double per energy
+  void local_dos(const rgf_device& d, z64* store, double* twos, double* dos, double* ados_l, double* ados_r,
+                 int32_t* info, bool same_leads);
   // lead-only output: copy sigma into the caller's dense [batch][M][M]
   void export_sigma(z64* sigma_ws, rgf_z* out);
   void lead_info(int side_bit, int32_t* done, int32_t* info);
@@ -81,6 +86,7 @@ class Engine {
   MatRef mref(z64* p, int64_t ld, int64_t bstride, const int32_t* ridx = nullptr) const;
   FillArgs fill_args(MatRef dst, int rows, int cols, int kind) const;
   double gemm(GemmArgs g, int prec, bool timed);
+  void ldos_pass(const rgf_device& d, z64* store, const double* twos, bool forward, double* dos, double* inj);
   FormRef gform(FormRef f) const {
     f.gper = gper_;
     f.gb0 = gb0_;
@@ -127,5 +133,8 @@ void run_device(const rgf_device& d, const double* E, int64_t nE, double eta, in
 void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
                        int32_t* info, hipStream_t st, double u_l = 0.0, double u_r = 0.0,
                        const Grouping& grp = Grouping());
+// orbital-resolved LDOS ([nE][N][M] each, any may be null), FP64, on one stream
+void ldos_impl(const rgf_device& d, const double* E, int64_t nE, double eta, double* dos, double* ados_l,
+               double* ados_r, int32_t* info, hipStream_t st);
 
 }  // namespace rgf

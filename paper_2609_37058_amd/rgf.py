@@ -76,6 +76,8 @@ SIGNATURES = {
                                         C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rgf_landauer_current": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_double,
                                        C.c_void_p, C.c_void_p]),
+    "rgf_ldos": (C.c_int, [C.POINTER(rgf_device), C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p,
+                           C.c_void_p, C.c_void_p, C.c_void_p]),
     "rgf_transmission_kmesh": (C.c_int, [C.POINTER(rgf_device), C.c_int32, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.c_void_p,
                                          C.c_int64, C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -202,6 +204,24 @@ def transmission_bias(dev: DeviceTensors, E: torch.Tensor, eta: float, u_left: f
     _check(lib.rgf_transmission_bias(C.byref(d), _ptr(E), nE, float(eta), float(u_left), float(u_right),
                                      PRECISION[precision], _ptr(out), _ptr(info), _stream(stream)))
     return out, info
+
+
+def ldos(dev: DeviceTensors, E: torch.Tensor, eta: float, parts=("dos", "left", "right"), stream=None):
+    """Orbital-resolved LDOS: (dos, ados_left, ados_right, info), each [nE, N, M] (None when not in parts)."""
+    lib = load()
+    E = E.contiguous()
+    nE = E.numel()
+    N, M = dev.N, dev.M
+    unknown = set(parts) - {"dos", "left", "right"}
+    if unknown or not parts:
+        raise ValueError(f"parts must be a non-empty subset of dos/left/right, got {parts}")
+    mk = lambda name: torch.empty((nE, N, M), dtype=torch.float64, device=E.device) if name in parts else None
+    dos, adl, adr = mk("dos"), mk("left"), mk("right")
+    info = torch.empty(nE, dtype=torch.int32, device=E.device)
+    d = dev.cstruct()
+    _check(lib.rgf_ldos(C.byref(d), _ptr(E), nE, float(eta), _ptr(dos), _ptr(adl), _ptr(adr), _ptr(info),
+                        _stream(stream)))
+    return dos, adl, adr, info
 
 
 def landauer_current(E: torch.Tensor, T: torch.Tensor, mu_left: float, mu_right: float, kT: float,
