@@ -40,3 +40,10 @@ from .ldos import (  # noqa: F401
     ldos_layers,
     device_matrix,
 )
+from .kpm import (  # noqa: F401
+    central_matrices,
+    jackson,
+    states_below,
+    fermi_level,
+)
+from . import kpm  # noqa: F401
