@@ -41,10 +41,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="block-product tile (64/128); 0 = library default")
-    ap.add_argument("--workload", choices=["c4", "bias", "kmesh", "ldos"], default="c4",
+    ap.add_argument("--workload", choices=["c4", "bias", "kmesh", "ldos", "kpm"], default="c4",
                     help="c4: the headline zero-bias workload; bias: the C4 device at finite bias with the "
                          "Landauer current; kmesh: a transversely periodic C2-type device on a 7x7 k-mesh; "
-                         "ldos: orbital-resolved LDOS and both injected parts of the C3 device")
+                         "ldos: orbital-resolved LDOS and both injected parts of the C3 device; "
+                         "kpm: Chebyshev moments and the Fermi level of the C4 central region")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (read once, written once), three "
                          "times, and exit: the reference kernel that scales the HBM byte counters")
@@ -184,6 +185,32 @@ def run_extra_workload(args) -> int:
                   "bias_V": V, "e_fermi": EF, "kT_eV": kT, "energy_window": [EF - half, EF + half],
                   "eta": cfg.eta, "precision": "fp64"}
         extra = {"current_A": float(I.item()), "nonzero_info": int((info != 0).sum().item())}
+    elif args.workload == "kpm":
+        # the C4 central region (400 layers, M = 1024): 256 Chebyshev moments from 64 random-phase
+        # vectors, then the Fermi level at half filling.  Spectral bounds: |e| <= ||H||_2 / lambda_min(S),
+        # with ||H||_2 <= ||H00|| + 2 ||H01|| + max |shift| and lambda_min(S) >= lambda_min(S00) - 2 ||S01||
+        cfg = synth.config_c4(n_e=1)
+        d = cfg.device
+        b = d.base
+        dev_t = staging.stage_repeated(b.H00, b.H01, b.S00, b.S01, d.N, d.shifts)
+        norm2 = lambda X: np.linalg.norm(X, 2)
+        h_norm = norm2(b.H00) + 2 * norm2(b.H01) + max([abs(v) for v in d.shifts.values()] + [0.0])
+        s_min = np.linalg.eigvalsh(b.S00)[0] - 2 * norm2(b.S01)
+        assert s_min > 0, "the overlap bound is not positive"
+        e_max = 1.01 * h_norm / s_min
+        n_mom, R = 256, 64
+        gen = torch.Generator(device="cpu").manual_seed(2024)
+        phases = torch.rand((d.N * d.M, R), generator=gen, dtype=torch.float64)
+        vec = torch.polar(torch.ones_like(phases), 2 * np.pi * phases).cuda()
+        n_states = d.N * d.M / 2
+        def step(k):
+            mu = rgf.kpm_moments(dev_t, -e_max, e_max, n_mom, vec)
+            return mu, rgf.kpm_fermi(mu, -e_max, e_max, n_states)
+        wall, lat, (mu, ef) = _timed_steps(step, args.steps, args.warmup)
+        units, unit = n_mom * R * d.N, "moment*vector*layers/s"
+        config = {"workload": "c4-kpm", "layers": d.N, "block": d.M, "moments": n_mom, "random_vectors": R,
+                  "spectral_bounds": [-e_max, e_max], "n_states": n_states, "precision": "fp64"}
+        extra = {"e_fermi": float(ef.item()), "mu0_over_dim": float(mu[0].item() / (d.N * d.M))}
     elif args.workload == "ldos":
         # the C3 device (200 layers, M = 512, 5% doped), LDOS and both injected parts per energy
         cfg = synth.config_c3()
@@ -198,7 +225,7 @@ def run_extra_workload(args) -> int:
         config = {"workload": "c3-ldos", "layers": d.N, "block": d.M, "energies_per_step": B,
                   "outputs": ["dos", "ados_left", "ados_right"], "eta": cfg.eta, "precision": "fp64"}
         extra = {"nonzero_info": int((info != 0).sum().item()),
-                 "sum_rule_max_rel": float(((dos - adl - adr).abs().max() / dos.abs().max()).item())}
+                 "dos_not_injected_max_rel": float(((dos - adl - adr).abs().max() / dos.abs().max()).item())}
     else:
         # C2-type device (60 random decay-weighted layers, M = 256) with transverse images along
         # both directions, on the 7x7 mesh of the paper's Pt-Si-Pt transport runs
@@ -231,8 +258,8 @@ def run_extra_workload(args) -> int:
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": config,
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "roofline": {"bound": "mfma", "kernel": ("LDOS block products" if args.workload == "ldos" else
-                                                 "sweep block product") + " (zgemm role 1)", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": {"ldos": "LDOS block products", "kpm": "Chebyshev-step products"}
+                     .get(args.workload, "sweep block product") + " (zgemm role 1)", "achieved": achieved,
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / FP64_MFMA_PEAK_TFLOPS) if achieved else None, "traffic": None,
                      "launches": n_launch, "avg_launch_ms": k_ms / max(1, n_launch)},

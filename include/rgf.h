@@ -205,6 +205,48 @@ int rgf_ldos(const rgf_device* dev, const double* E, int64_t nE, double eta, dou
              double* ados_right, int32_t* info, void* stream);
 
 /*
+ * rgf_kpm_moments -- Chebyshev moments of the nonorthogonal kernel polynomial
+ * method (paper: Introduction and Results -- the rescaled operator
+ * S^-1 (H - b S) / a of the central region, S applied through linear solves,
+ * random vectors, cost O(N_mom N_rand N); textbook KPM: Weisse et al., Rev.
+ * Mod. Phys. 78, 275 (2006)).  The central region is the device blocks of dev
+ * (Hd, Hu, Sd, Su as in rgf_transmission; the electrode blocks are not read).
+ * With a = (e_max - e_min) / (2 - 0.01), b = (e_max + e_min) / 2 and the
+ * R random vectors r_j = columns of vectors[(l M + m) R + j] (DEVICE,
+ * complex, the caller draws them, e.g. random phases):
+ *   mu[n] = Re sum_j r_j^+ T_n(A~) r_j / R,  A~ = S^-1 (H - b S) / a,
+ * for n < n_mom (DEVICE array of doubles).  [e_min, e_max] must enclose the
+ * spectrum of (H, S).  S is factored once per call (block Thomas, FP64;
+ * RGF_EINVAL if a pivot is exactly zero).  The library keeps 3 N Mp^2 complex
+ * factors and 5 N Mp Rp complex vector panels (Mp, Rp = M, R rounded up to
+ * 64) in a workspace per stream.  Stream-ordered (blocks for the S check);
+ * RGF_EINVAL for null pointers, N < 1, M outside [1, 2048], n_mom < 1, R < 1
+ * or bad bounds.
+ */
+int rgf_kpm_moments(const rgf_device* dev, double e_min, double e_max, int32_t n_mom, const rgf_z* vectors,
+                    int32_t R, double* mu, void* stream);
+
+/*
+ * rgf_kpm_fermi -- the Fermi level from KPM moments by the electron-number
+ * constraint (paper: Introduction): with the Jackson kernel g_n,
+ *   N(x) = g_0 mu_0 (pi - acos x) / pi - (2/pi) sum_{n>=1} g_n mu_n sin(n acos x) / n
+ * counts the states below x = (e - b) / a; e_fermi[0] (DEVICE) receives
+ * a x_F + b with N(x_F) = n_states (occupied states, spin not counted), by
+ * bisection on [-1, 1] in one workgroup.  mu: DEVICE [n_mom].  Same a, b as
+ * rgf_kpm_moments.  Stream-ordered.
+ */
+int rgf_kpm_fermi(const double* mu, int32_t n_mom, double e_min, double e_max, double n_states, double* e_fermi,
+                  void* stream);
+
+/*
+ * rgf_kpm_dos -- the kernel-smoothed density of states per unit energy,
+ *   rho(E) = [g_0 mu_0 + 2 sum_{n>=1} g_n mu_n T_n(x)] / (pi a sqrt(1 - x^2)),
+ * x = (E - b) / a, at E[nE] into dos[nE] (DEVICE pointers).  Stream-ordered.
+ */
+int rgf_kpm_dos(const double* mu, int32_t n_mom, double e_min, double e_max, const double* E, int64_t nE,
+                double* dos, void* stream);
+
+/*
  * lead_self_energy -- Sigma of one lead for side RGF_LEFT (L g_L U) or
  * RGF_RIGHT (U g_R L), written to sigma[nE][M][M] (device pointer, row-major,
  * device-side block).  Same pointer, stream and info conventions as

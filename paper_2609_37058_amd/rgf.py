@@ -76,6 +76,12 @@ SIGNATURES = {
                                         C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rgf_landauer_current": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_double,
                                        C.c_void_p, C.c_void_p]),
+    "rgf_kpm_moments": (C.c_int, [C.POINTER(rgf_device), C.c_double, C.c_double, C.c_int32, C.c_void_p,
+                                  C.c_int32, C.c_void_p, C.c_void_p]),
+    "rgf_kpm_fermi": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                C.c_void_p]),
+    "rgf_kpm_dos": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_int64, C.c_void_p,
+                              C.c_void_p]),
     "rgf_ldos": (C.c_int, [C.POINTER(rgf_device), C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p, C.c_void_p]),
     "rgf_transmission_kmesh": (C.c_int, [C.POINTER(rgf_device), C.c_int32, C.POINTER(C.c_int32),
@@ -222,6 +228,40 @@ def ldos(dev: DeviceTensors, E: torch.Tensor, eta: float, parts=("dos", "left", 
     _check(lib.rgf_ldos(C.byref(d), _ptr(E), nE, float(eta), _ptr(dos), _ptr(adl), _ptr(adr), _ptr(info),
                         _stream(stream)))
     return dos, adl, adr, info
+
+
+def kpm_moments(dev: DeviceTensors, e_min: float, e_max: float, n_mom: int, vectors: torch.Tensor,
+                stream=None) -> torch.Tensor:
+    """Chebyshev moments [n_mom] of S^-1 (H - b S) / a of the device blocks; vectors: [N*M, R] complex128."""
+    lib = load()
+    vectors = vectors.contiguous()
+    if vectors.dtype != torch.complex128 or vectors.dim() != 2 or vectors.shape[0] != dev.N * dev.M:
+        raise ValueError("vectors must be complex128 of shape [N*M, R]")
+    mu = torch.empty(int(n_mom), dtype=torch.float64, device=vectors.device)
+    d = dev.cstruct()
+    _check(lib.rgf_kpm_moments(C.byref(d), float(e_min), float(e_max), int(n_mom), _ptr(vectors),
+                               int(vectors.shape[1]), _ptr(mu), _stream(stream)))
+    return mu
+
+
+def kpm_fermi(mu: torch.Tensor, e_min: float, e_max: float, n_states: float, stream=None) -> torch.Tensor:
+    """The Fermi level (a one-element device tensor) at which the Jackson-smoothed state count is n_states."""
+    lib = load()
+    mu = mu.contiguous()
+    ef = torch.empty(1, dtype=torch.float64, device=mu.device)
+    _check(lib.rgf_kpm_fermi(_ptr(mu), mu.numel(), float(e_min), float(e_max), float(n_states), _ptr(ef),
+                             _stream(stream)))
+    return ef
+
+
+def kpm_dos(mu: torch.Tensor, e_min: float, e_max: float, E: torch.Tensor, stream=None) -> torch.Tensor:
+    """Jackson-smoothed density of states per unit energy at the energies E."""
+    lib = load()
+    mu, E = mu.contiguous(), E.contiguous()
+    out = torch.empty(E.numel(), dtype=torch.float64, device=E.device)
+    _check(lib.rgf_kpm_dos(_ptr(mu), mu.numel(), float(e_min), float(e_max), _ptr(E), E.numel(), _ptr(out),
+                           _stream(stream)))
+    return out
 
 
 def landauer_current(E: torch.Tensor, T: torch.Tensor, mu_left: float, mu_right: float, kT: float,

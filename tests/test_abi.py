@@ -56,6 +56,10 @@ def test_argument_errors_before_device_work(lib):
     assert L.rgf_set_tile(0, 96) == rgf.RGF_EINVAL
     assert L.rgf_set_mixed_parts(8) == rgf.RGF_EINVAL
     assert L.rgf_version().startswith(b"librgf")
+    assert L.rgf_ldos(C.byref(d), None, 1, 1e-6, None, None, None, None, None) == rgf.RGF_EINVAL
+    assert L.rgf_kpm_moments(None, -1.0, 1.0, 10, None, 4, None, None) == rgf.RGF_EINVAL
+    assert L.rgf_kpm_fermi(None, 10, 1.0, -1.0, 3.0, None, None) == rgf.RGF_EINVAL
+    assert L.rgf_kpm_dos(None, 0, -1.0, 1.0, None, 5, None, None) == rgf.RGF_EINVAL
 
 
 def test_tuning_table_on_the_host(tmp_path):
