@@ -14,6 +14,9 @@
 //                                forward  Z_i = W_i - Lf_i Z_{i-1},
 //                                then     X = Dinv Z (one batched product),
 //                                back     X_i = X_i - Uf_i X_{i+1},
+//                                each sweep step split over chunks of its
+//                                inner dimension (partial products in one
+//                                launch, then a fixed-order sum),
 //                                with D_0 = S_00, D_i = S_ii - S_{i,i-1} Uf_{i-1},
 //                                Dinv_i = D_i^-1, Uf_i = D_i^-1 S_{i,i+1},
 //                                Lf_i = S_{i,i-1} D_{i-1}^-1 (factored once per call)
@@ -22,6 +25,7 @@
 // The sweeps of the solve are sequential over the layers (one product of an
 // M x M factor with an M x R panel each), the rest is batched over layers.
 // Every sum runs in a fixed order, so the moments do not depend on the launch.
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -90,6 +94,20 @@ __global__ void __launch_bounds__(256) kpm_moment_kernel(const double* partial, 
     __syncthreads();
   }
   if (threadIdx.x == 0) *mu = red[0] * inv_r;
+}
+
+// C[i] -= sum_c partial[c][i], c = 0..nc-1 in order (the split-K partial products of a sweep step)
+__global__ void kpm_ksum_kernel(z64* C, const z64* partial, int nc, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < nc; ++c) {
+    const z64 p = partial[(int64_t)c * n + i];
+    re += p.x;
+    im += p.y;
+  }
+  const z64 v = C[i];
+  C[i] = zmake(v.x - re, v.y - im);
 }
 
 __device__ inline double jackson_g(int n, int N) {
@@ -189,6 +207,31 @@ void timed_gemm(const GemmArgs& g, hipStream_t st) {
   }
 }
 
+// Chunks of the inner dimension for a sweep step: enough (Mp/64 x Rp/64 x nc)
+// workgroups to fill the chip, nc dividing Mp / 16.
+int ksplit(int Mp, int Rp) {
+  const int tiles = (Mp / 64) * (Rp / 64);
+  int nc = std::min(Mp / 16, std::max(1, 256 / tiles));
+  while ((Mp / 16) % nc) --nc;
+  return nc;
+}
+
+// One step of a solve sweep, C = C - A B (A: Mp x Mp, B, C: Mp x Rp panels), as
+// nc partial products over chunks of the inner dimension (one batched launch,
+// so a single sequential step still spreads over the chip) and a fixed-order sum.
+void sweep_step(const z64* A, const z64* Bp, z64* Cp, z64* partial, int Mp, int Rp, hipStream_t st) {
+  const int nc = ksplit(Mp, Rp);
+  const int kc = Mp / nc;
+  GemmArgs g = product(Mp, Rp, kc, nc);
+  g.A = mat(const_cast<z64*>(A), kc, Mp);
+  g.B = mat(const_cast<z64*>(Bp), (int64_t)kc * Rp, Rp);
+  g.C = mat(partial, (int64_t)Mp * Rp, Rp);
+  timed_gemm(g, st);
+  const int64_t n = (int64_t)Mp * Rp;
+  hipLaunchKernelGGL(kpm_ksum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Cp, partial, nc, n);
+  RGF_HIP(hipGetLastError());
+}
+
 struct KpmArena {
   char* p = nullptr;
   size_t bytes = 0;
@@ -224,6 +267,7 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
   const size_t o_perm = take(4 * Mp), o_cand = take(4 * Mp), o_flags = take(Mp), o_sing = take(4);
   const size_t o_bv = take(sizeof(double) * N), o_two = take(sizeof(double) * N);
   const size_t o_part = take(sizeof(double) * DOT_BLOCKS);
+  const size_t o_ksplit = take(sizeof(z64) * (size_t)ksplit(Mp, Rp) * Mp * Rp);
   int dev = 0;
   RGF_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_kpm_mu);
@@ -259,6 +303,7 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
   double* bvals = reinterpret_cast<double*>(base + o_bv);
   double* twos = reinterpret_cast<double*>(base + o_two);
   double* partial = reinterpret_cast<double*>(base + o_part);
+  z64* kpart = reinterpret_cast<z64*>(base + o_ksplit);
   hipLaunchKernelGGL(kpm_fill_kernel, dim3((N + 255) / 256), dim3(256), 0, st, bvals, N, b);
   hipLaunchKernelGGL(kpm_fill_kernel, dim3((N + 255) / 256), dim3(256), 0, st, twos, N, 2.0);
   RGF_HIP(hipMemsetAsync(lu.sing, 0, sizeof(int32_t), st));
@@ -365,32 +410,14 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
       timed_gemm(g, st);
     }
     // forward sweep Z_i = W_i - Lf_i Z_{i-1}
-    for (int i = 1; i < N; ++i) {
-      GemmArgs f = product(Mp, Rp, Mp, 1);
-      f.A = mat1(Lf + i * MM, Mp);
-      f.B = panel(W, i - 1);
-      f.c_kind = SRC_MAT;
-      f.Cin = panel(W, i);
-      f.C = panel(W, i);
-      f.alpha = -1.0;
-      timed_gemm(f, st);
-    }
+    for (int i = 1; i < N; ++i) sweep_step(Lf + i * MM, W + (i - 1) * VB, W + i * VB, kpart, Mp, Rp, st);
     // X = Dinv Z, then the back sweep X_i = X_i - Uf_i X_{i+1}
     g = product(Mp, Rp, Mp, N);
     g.A = mat(Dinv, MM, Mp);
     g.B = panel(W, 0);
     g.C = panel(X, 0);
     timed_gemm(g, st);
-    for (int i = N - 2; i >= 0; --i) {
-      GemmArgs f = product(Mp, Rp, Mp, 1);
-      f.A = mat1(Uf + i * MM, Mp);
-      f.B = panel(X, i + 1);
-      f.c_kind = SRC_MAT;
-      f.Cin = panel(X, i);
-      f.C = panel(X, i);
-      f.alpha = -1.0;
-      timed_gemm(f, st);
-    }
+    for (int i = N - 2; i >= 0; --i) sweep_step(Uf + i * MM, X + (i + 1) * VB, X + i * VB, kpart, Mp, Rp, st);
     moment(X, vprev, mu + n + 1);
     vprev = vcur;
     vcur = X;
