@@ -186,7 +186,7 @@ def run_extra_workload(args) -> int:
                   "eta": cfg.eta, "precision": "fp64"}
         extra = {"current_A": float(I.item()), "nonzero_info": int((info != 0).sum().item())}
     elif args.workload == "kpm":
-        # the C4 central region (400 layers, M = 1024): 256 Chebyshev moments from 64 random-phase
+        # the C4 central region (400 layers, M = 1024): 512 Chebyshev moments from 64 random-phase
         # vectors, then the Fermi level at half filling.  Spectral bounds: |e| <= ||H||_2 / lambda_min(S),
         # with ||H||_2 <= ||H00|| + 2 ||H01|| + max |shift| and lambda_min(S) >= lambda_min(S00) - 2 ||S01||
         cfg = synth.config_c4(n_e=1)
@@ -198,7 +198,7 @@ def run_extra_workload(args) -> int:
         s_min = np.linalg.eigvalsh(b.S00)[0] - 2 * norm2(b.S01)
         assert s_min > 0, "the overlap bound is not positive"
         e_max = 1.01 * h_norm / s_min
-        n_mom, R = 256, 64
+        n_mom, R = 512, 64
         gen = torch.Generator(device="cpu").manual_seed(2024)
         phases = torch.rand((d.N * d.M, R), generator=gen, dtype=torch.float64)
         vec = torch.polar(torch.ones_like(phases), 2 * np.pi * phases).cuda()
@@ -217,7 +217,7 @@ def run_extra_workload(args) -> int:
         d = cfg.device
         b = d.base
         dev_t = staging.stage_repeated(b.H00, b.H01, b.S00, b.S01, d.N, d.shifts)
-        B = min(args.energies_per_step, 32)
+        B = min(args.energies_per_step, 64)
         E = torch.linspace(-0.5, 0.5, B, dtype=torch.float64, device="cuda")
         step = lambda k: rgf.ldos(dev_t, E, cfg.eta)
         wall, lat, (dos, adl, adr, info) = _timed_steps(step, args.steps, args.warmup)
@@ -386,6 +386,20 @@ def main():
         },
         "nonzero_info": head["nonzero_info"],
     }
+    if "fp64" in results:
+        # the decimation and self-energy part alone (one electrode; the device's two are the same
+        # electrode, so the sweep shares one decimation): one step's energies, HIP-event timed
+        Eb = E_all[:B]
+        rgf.lead_self_energy(dev_t.left, 0, Eb, cfg.eta)  # workspace set-up, untimed
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        rgf.lead_self_energy(dev_t.left, 0, Eb, cfg.eta)
+        ev1.record(stream)
+        ev1.synchronize()
+        sr_ms = ev0.elapsed_time(ev1)
+        out["parts_ms_per_step"] = {"self_energy_alone": sr_ms,
+                                    "sweep_and_trace": results["fp64"]["ms_per_step"] - sr_ms}
     if "mixed" in results and "fp64" in results:
         m = results["mixed"]
         out["mixed"] = {"value": m["value"], "ms_per_step": m["ms_per_step"],

@@ -292,7 +292,8 @@ int transport_stats(void* server, rgf_server_stats* stats);
 const char* rgf_last_error(void);
 const char* rgf_version(void);
 
-/* Release every cached device workspace of the current device. */
+/* Release every cached device workspace of the current device (sweep workspaces, batch job
+   buffers, k-mesh and KPM arenas); synchronizes the device first. */
 int rgf_release_workspaces(void);
 
 /*
@@ -307,8 +308,10 @@ int rgf_profile(int enable);
 int rgf_profile_read(int64_t* launches, double* total_ms, double* flops);
 
 /* Tile configuration of the FP64 and mixed block products: 128 (128x128 output
- * tiles, 64-row tiles for 64-row products) or 64 (64x64 tiles).  Applies to later
- * calls in the process. */
+ * tiles, 64-row tiles for 64-row products) or 64 (64x64 tiles).  rgf_set_tile
+ * sets one tile for every size (replacing the built-in per-size choice and any
+ * rgf_set_tuning tile); rgf_get_tile reports it (128 while none was set).
+ * Applies to later calls in the process. */
 int rgf_get_tile(int precision, int32_t* tile);
 int rgf_set_tile(int precision, int32_t tile);
 
@@ -317,8 +320,9 @@ int rgf_set_tile(int precision, int32_t tile);
  * block size class Mp = ceil(M/64)*64 and precision, the library keeps the
  * block-product tile (64 or 128) and the number of energy lanes (internal
  * streams, each driven by its own host thread, over which one call splits its
- * energies).  0 means the built-in default (tile: the rgf_set_tile value;
- * lanes: 2 from Mp = 256, else 1).  A setting depends only on (M, precision),
+ * energies).  0 means the built-in default (tile: the rgf_set_tile value if one
+ * was set, else 128 except 64 for FP64 at Mp = 256, the measured faster choice
+ * there; lanes: 2 from Mp = 256, else 1).  A setting depends only on (M, precision),
  * never on the batch, so a result does not depend on which energies share a
  * call.  rgf_get_tuning reports the values in effect (defaults resolved);
  * rgf_set_tuning returns RGF_EINVAL for M outside [1, 2048], a tile other than

@@ -133,6 +133,10 @@ void run_device(const rgf_device& d, const double* E, int64_t nE, double eta, in
 void transmission_impl(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
                        int32_t* info, hipStream_t st, double u_l = 0.0, double u_r = 0.0,
                        const Grouping& grp = Grouping());
+// free the k-mesh and KPM arenas held for device `dev` (the caller has synchronized it)
+void release_kmesh_arenas(int dev);
+void release_kpm_arenas(int dev);
+
 // orbital-resolved LDOS ([nE][N][M] each, any may be null), FP64, on one stream
 void ldos_impl(const rgf_device& d, const double* E, int64_t nE, double eta, double* dos, double* ados_l,
                double* ados_r, int32_t* info, hipStream_t st);

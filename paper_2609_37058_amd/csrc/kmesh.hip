@@ -38,6 +38,20 @@ bool same_ptrs(const rgf_lead& a, const rgf_lead& b) {
 }
 
 }  // namespace
+
+void release_kmesh_arenas(int dev) {
+  std::lock_guard<std::mutex> lk(g_kmu);
+  for (auto it = g_karena.begin(); it != g_karena.end();) {
+    if (it->first.first == dev) {
+      if (it->second.done) RGF_HIP(hipEventDestroy(it->second.done));
+      if (it->second.p) RGF_HIP(hipFree(it->second.p));
+      it = g_karena.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
 }  // namespace rgf
 
 using namespace rgf;

@@ -241,6 +241,18 @@ std::map<std::pair<int, hipStream_t>, KpmArena> g_kpm;
 
 }  // namespace
 
+void release_kpm_arenas(int dev) {
+  std::lock_guard<std::mutex> lk(g_kpm_mu);
+  for (auto it = g_kpm.begin(); it != g_kpm.end();) {
+    if (it->first.first == dev) {
+      if (it->second.p) RGF_HIP(hipFree(it->second.p));
+      it = g_kpm.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
 // Moments of one central region (blocks of `d`; its electrodes are not used).
 void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom, const rgf_z* vectors, int R,
                       double* mu, hipStream_t st) {

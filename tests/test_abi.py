@@ -68,6 +68,8 @@ def test_tuning_table_on_the_host(tmp_path):
     rgf.load()
     assert rgf.get_tuning(100, "fp64") == (128, 1)      # defaults: 128 tiles, one lane below Mp = 256
     assert rgf.get_tuning(1024, "mixed") == (128, 2)
+    assert rgf.get_tuning(256, "fp64") == (64, 2)       # the measured built-in choice at Mp = 256
+    assert rgf.get_tuning(256, "mixed") == (128, 2)
     rgf.set_tuning(100, "fp64", 64, 2)
     assert rgf.get_tuning(128, "fp64") == (64, 2)       # same padded size class
     assert rgf.get_tuning(129, "fp64") == (128, 1)

@@ -76,7 +76,7 @@ def test_ldos_sampled_layers_of_a_c2_sized_device(lib):
     assert all(ok) and np.all(info == 0)
 
 
-def test_ldos_parts_and_chunks_are_bitwise_equal(lib, monkeypatch):
+def test_ldos_parts_chunks_and_lanes_are_bitwise_equal(lib, monkeypatch):
     dev_t = stage(synth.random_small_device(4, 40, seed=81, distinct_leads=True))
     E = np.linspace(-1.0, 1.0, 7)
     full = run(lib, dev_t, E)
@@ -85,10 +85,12 @@ def test_ldos_parts_and_chunks_are_bitwise_equal(lib, monkeypatch):
         for name, a, b in zip(("dos", "left", "right"), full[:3], sub[:3]):
             if name in parts:
                 assert np.array_equal(a, b), (parts, name)
-    monkeypatch.setenv("RGF_MAX_CHUNK", "3")
-    chunked = run(lib, dev_t, E)
-    for a, b in zip(full, chunked):
-        assert np.array_equal(a, b)
+    for chunk, lanes in (("3", "1"), ("2", "2"), ("7", "3")):
+        monkeypatch.setenv("RGF_MAX_CHUNK", chunk)
+        monkeypatch.setenv("RGF_LANES", lanes)
+        chunked = run(lib, dev_t, E)
+        for a, b in zip(full, chunked):
+            assert np.array_equal(a, b), (chunk, lanes)
 
 
 def test_ldos_argument_errors(lib):
