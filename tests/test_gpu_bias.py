@@ -36,6 +36,26 @@ def test_bias_transmission_matches_oracle(lib, N, M, distinct):
         assert ok and np.all(info == 0)
 
 
+def _decay_device(N, M, seed):
+    """Decay-weighted random layers with a separate electrode (the C2 recipe: S positive definite)."""
+    layers = [synth.decay_layer(seed, i, M) for i in range(N)]
+    lead = synth.decay_layer(seed + 100, 0, M)
+    return synth.device_from_blocks([l.H00 for l in layers], [l.H01 for l in layers[:-1]],
+                                    [l.S00 for l in layers], [l.S01 for l in layers[:-1]], lead, lead)
+
+
+@pytest.mark.parametrize("N,M", [(4, 40), (3, 130)])
+def test_bias_mixed_precision_within_the_mixed_bar(lib, N, M):
+    """The precision form at finite bias: |dT| <= 1e-4 against the FP64 oracle (on the
+    well-conditioned decay-weighted recipe the bar is stated for)."""
+    dev = _decay_device(N, M, seed=350 + M)
+    E = np.array([-1.2, -0.3, 0.4, 1.3])
+    T, info = _bias(lib, stage(dev), E, 1e-6, 0.1, -0.1, "mixed")
+    ref = oracle.transmission_bias(dev, E, 1e-6, 0.1, -0.1)
+    log(f"[bias] mixed N={N} M={M}: max |dT| {np.abs(T - ref).max():.2e}")
+    assert np.all(np.abs(T - ref) <= 1e-4) and np.all(info == 0)
+
+
 def test_bias_small_block_path_and_batched_path_agree(lib):
     dev = synth.random_small_device(6, 7, seed=71)
     dt = stage(dev)
