@@ -58,7 +58,7 @@ def test_gemm_matches_numpy(kt, prec, tile, rows, cols, K, batch):
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("Mp,nrhs,batch", [(64, 64, 2), (128, 128, 3), (192, 384, 2), (256, 256, 1), (512, 128, 2),
-                                           (576, 64, 2), (1024, 128, 2)])
+                                           (576, 64, 2), (1024, 128, 2), (1152, 64, 2), (2048, 64, 1)])
 def test_lu_solve_matches_numpy_solve(kt, prec, Mp, nrhs, batch):
     import torch
     rng = np.random.default_rng(Mp + nrhs)

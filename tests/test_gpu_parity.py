@@ -69,3 +69,18 @@ def test_lead_self_energy_matches_oracle(lib):
             log(f"[parity] sigma side={side} E={e}: rel {err:.2e}")
             assert err < 1e-9
         assert np.all(info.cpu().numpy() == 0)
+
+
+def test_blocks_above_1024(lib):
+    """M = 1100 (padded 1152: the four-rows-per-thread panel) against the oracle; a broad eta keeps
+    the oracle's decimation of the 1100-orbital electrode short."""
+    layers = [synth.decay_layer(61, i, 1100) for i in range(2)]
+    lead = synth.decay_layer(161, 0, 1100)
+    dev = synth.device_from_blocks([l.H00 for l in layers], [layers[0].H01], [l.S00 for l in layers],
+                                   [layers[0].S01], lead, lead)
+    E = np.array([-0.4, 0.7])
+    T, info = gpu_transmission(stage(dev), E, 0.05)
+    ref = oracle.transmission(dev, E, 0.05, method="thomas")
+    ok, rel, ab = fp64_close(T, ref)
+    log(f"[parity] M=1100: max rel {rel:.2e} max abs {ab:.2e}")
+    assert ok and np.all(info == 0)
