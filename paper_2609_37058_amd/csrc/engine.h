@@ -84,7 +84,6 @@ class Engine {
 
  private:
   MatRef mref(z64* p, int64_t ld, int64_t bstride, const int32_t* ridx = nullptr) const;
-  FillArgs fill_args(MatRef dst, int rows, int cols, int kind) const;
   double gemm(GemmArgs g, int prec, bool timed);
   void ldos_pass(const rgf_device& d, z64* store, const double* twos, bool forward, double* dos, double* inj);
   FormRef gform(FormRef f) const {

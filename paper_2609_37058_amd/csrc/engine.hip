@@ -129,43 +129,6 @@ double Engine::gemm(GemmArgs g, int prec, bool timed) {
   return launch_gemm(g, prec, tile_for(prec, Mp_), st_, role);
 }
 
-static GemmArgs gemm_args(int rows, int cols, int K, int batch) {
-  GemmArgs g;
-  g.rows = rows;
-  g.cols = cols;
-  g.K = K;
-  g.batch = batch;
-  g.a_kind = SRC_MAT;
-  g.A = nomat();
-  g.Af = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
-  g.B = nomat();
-  g.c_kind = SRC_NONE;
-  g.Cin = nomat();
-  g.Cf = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
-  g.C = nomat();
-  g.alpha = 1.0;
-  g.ctl.skip = nullptr;
-  return g;
-}
-
-FillArgs Engine::fill_args(MatRef dst, int rows, int cols, int kind) const {
-  FillArgs f;
-  f.dst = dst;
-  f.rows = rows;
-  f.cols = cols;
-  f.kind = kind;
-  f.scale = 1.0;
-  f.src = nomat();
-  f.f = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
-  f.flags = nullptr;
-  f.flags_bs = 0;
-  f.flags_n = 0;
-  f.ridx = nullptr;
-  f.ridx_bs = 0;
-  f.ctl.skip = nullptr;
-  return f;
-}
-
 void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
   const int Mp = Mp_;
   const double* El = left ? EL_ : ER_;

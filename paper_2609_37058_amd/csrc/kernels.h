@@ -55,6 +55,27 @@ struct GemmArgs {
   BatchCtl ctl;
 };
 
+// A product of rows x cols outputs with inner dimension K over `batch` entries,
+// every operand unset (A, B, Cin and C are filled in by the caller), alpha = 1.
+inline GemmArgs gemm_args(int rows, int cols, int K, int batch, const int32_t* skip = nullptr) {
+  GemmArgs g;
+  g.rows = rows;
+  g.cols = cols;
+  g.K = K;
+  g.batch = batch;
+  g.a_kind = SRC_MAT;
+  g.A = nomat();
+  g.Af = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
+  g.B = nomat();
+  g.c_kind = SRC_NONE;
+  g.Cin = nomat();
+  g.Cf = g.Af;
+  g.C = nomat();
+  g.alpha = 1.0;
+  g.ctl.skip = skip;
+  return g;
+}
+
 // tile = 64 or 128 (square output tiles); role 1 marks the sweep's main block
 // products (a separate kernel symbol, so profiles can single them out).
 // Returns the algorithmic flops launched.
@@ -115,6 +136,24 @@ struct FillArgs {
   BatchCtl ctl;
 };
 void launch_fill(const FillArgs& a, int batch, hipStream_t st);
+// A fill of `kind` into dst (rows x cols) with no source, no row gather and scale 1.
+inline FillArgs fill_args(MatRef dst, int rows, int cols, int kind) {
+  FillArgs f;
+  f.dst = dst;
+  f.rows = rows;
+  f.cols = cols;
+  f.kind = kind;
+  f.scale = 1.0;
+  f.src = nomat();
+  f.f = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
+  f.flags = nullptr;
+  f.flags_bs = 0;
+  f.flags_n = 0;
+  f.ridx = nullptr;
+  f.ridx_bs = 0;
+  f.ctl.skip = nullptr;
+  return f;
+}
 // synthetic inputs: p[i] = scale (u + i v) (+ diag on block diagonals), u, v uniform in [-1, 1)
 void launch_random(z64* p, int64_t n, int64_t ld, int64_t rows, double scale, double diag, uint64_t seed,
                    hipStream_t st);

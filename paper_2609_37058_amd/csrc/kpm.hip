@@ -159,43 +159,6 @@ __global__ void kpm_dos_kernel(const double* mu, int nm, double a, double b, con
   out[k] = s / (3.14159265358979323846 * sqrt(fmax(1.0 - x * x, 1e-300)) * a);
 }
 
-GemmArgs product(int rows, int cols, int K, int batch) {
-  GemmArgs g;
-  g.rows = rows;
-  g.cols = cols;
-  g.K = K;
-  g.batch = batch;
-  g.a_kind = SRC_MAT;
-  g.A = nomat();
-  g.Af = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
-  g.B = nomat();
-  g.c_kind = SRC_NONE;
-  g.Cin = nomat();
-  g.Cf = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
-  g.C = nomat();
-  g.alpha = 1.0;
-  g.ctl.skip = nullptr;
-  return g;
-}
-
-FillArgs fill(MatRef dst, int rows, int cols, int kind) {
-  FillArgs f;
-  f.dst = dst;
-  f.rows = rows;
-  f.cols = cols;
-  f.kind = kind;
-  f.scale = 1.0;
-  f.src = nomat();
-  f.f = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
-  f.flags = nullptr;
-  f.flags_bs = 0;
-  f.flags_n = 0;
-  f.ridx = nullptr;
-  f.ridx_bs = 0;
-  f.ctl.skip = nullptr;
-  return f;
-}
-
 // the Chebyshev step's products, timed per launch when profiling is on
 void timed_gemm(const GemmArgs& g, hipStream_t st) {
   if (profiling()) {
@@ -222,7 +185,7 @@ int ksplit(int Mp, int Rp) {
 void sweep_step(const z64* A, const z64* Bp, z64* Cp, z64* partial, int Mp, int Rp, hipStream_t st) {
   const int nc = ksplit(Mp, Rp);
   const int kc = Mp / nc;
-  GemmArgs g = product(Mp, Rp, kc, nc);
+  GemmArgs g = gemm_args(Mp, Rp, kc, nc);
   g.A = mat(const_cast<z64*>(A), kc, Mp);
   g.B = mat(const_cast<z64*>(Bp), (int64_t)kc * Rp, Rp);
   g.C = mat(partial, (int64_t)Mp * Rp, Rp);
@@ -327,11 +290,11 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
   // ---- block-Thomas factors of S ----
   for (int i = 0; i < N; ++i) {
     if (i == 0) {
-      FillArgs f = fill(mat1(T, Mp), Mp, Mp, FILL_FORM);
+      FillArgs f = fill_args(mat1(T, Mp), Mp, Mp, FILL_FORM);
       f.f = sblk(d.Sd, false, true);
       launch_fill(f, 1, st);
     } else {  // D_i = S_ii - S_{i,i-1} Uf_{i-1}
-      GemmArgs g = product(Mp, Mp, Mp, 1);
+      GemmArgs g = gemm_args(Mp, Mp, Mp, 1);
       g.a_kind = SRC_FORM;
       g.Af = sblk(d.Su + (i - 1) * M2, true, false);
       g.B = mat1(Uf + (i - 1) * MM, Mp);
@@ -342,19 +305,19 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
       launch_gemm(g, PREC_F64, tile, st);
     }
     lu_factor(lu, T, MM, Mp, 1, nullptr, i + 1, PREC_F64, tile, st);
-    FillArgs f = fill(mat1(Dinv + i * MM, Mp), Mp, Mp, FILL_IDENTITY);
+    FillArgs f = fill_args(mat1(Dinv + i * MM, Mp), Mp, Mp, FILL_IDENTITY);
     f.ridx = lu.perm;
     f.ridx_bs = Mp;
     launch_fill(f, 1, st);
     lu_solve(lu, T, MM, Mp, Dinv + i * MM, MM, Mp, 1, nullptr, PREC_F64, tile, st);
     if (i + 1 < N) {
-      f = fill(mat1(Uf + i * MM, Mp), Mp, Mp, FILL_FORM);
+      f = fill_args(mat1(Uf + i * MM, Mp), Mp, Mp, FILL_FORM);
       f.f = sblk(d.Su + i * M2, false, false);
       f.ridx = lu.perm;
       f.ridx_bs = Mp;
       launch_fill(f, 1, st);
       lu_solve(lu, T, MM, Mp, Uf + i * MM, MM, Mp, 1, nullptr, PREC_F64, tile, st);
-      GemmArgs g = product(Mp, Mp, Mp, 1);  // Lf_{i+1} = S_{i+1,i} Dinv_i
+      GemmArgs g = gemm_args(Mp, Mp, Mp, 1);  // Lf_{i+1} = S_{i+1,i} Dinv_i
       g.a_kind = SRC_FORM;
       g.Af = sblk(d.Su + i * M2, true, false);
       g.B = mat1(Dinv + i * MM, Mp);
@@ -398,7 +361,7 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
     z64* X = ring[n % 3];
     const double alpha = (n == 0 ? -1.0 : -2.0) / a;  // c (H - b S) / a = -(c / a) (b S - H)
     // W = c (H - b S) V / a: diagonal, upper and lower blocks
-    GemmArgs g = product(Mp, Rp, Mp, N);
+    GemmArgs g = gemm_args(Mp, Rp, Mp, N);
     g.a_kind = SRC_FORM;
     g.Af = grouped(form(d.Hd, d.Sd, M, false, false, bvals, 0.0));
     g.B = panel(vcur, 0);
@@ -406,7 +369,7 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
     g.alpha = alpha;
     timed_gemm(g, st);
     if (N > 1) {
-      g = product(Mp, Rp, Mp, N - 1);
+      g = gemm_args(Mp, Rp, Mp, N - 1);
       g.a_kind = SRC_FORM;
       g.Af = grouped(form(d.Hu, d.Su, M, false, false, bvals, 0.0));
       g.B = panel(vcur, 1);
@@ -424,7 +387,7 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
     // forward sweep Z_i = W_i - Lf_i Z_{i-1}
     for (int i = 1; i < N; ++i) sweep_step(Lf + i * MM, W + (i - 1) * VB, W + i * VB, kpart, Mp, Rp, st);
     // X = Dinv Z, then the back sweep X_i = X_i - Uf_i X_{i+1}
-    g = product(Mp, Rp, Mp, N);
+    g = gemm_args(Mp, Rp, Mp, N);
     g.A = mat(Dinv, MM, Mp);
     g.B = panel(W, 0);
     g.C = panel(X, 0);

@@ -119,23 +119,6 @@ void launch_proj(const ProjArgs& a, bool rows, int batch, hipStream_t st) {
   RGF_HIP(hipGetLastError());
 }
 
-GemmArgs product(int Mp, int batch) {
-  GemmArgs g;
-  g.rows = g.cols = g.K = Mp;
-  g.batch = batch;
-  g.a_kind = SRC_MAT;
-  g.A = nomat();
-  g.Af = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
-  g.B = nomat();
-  g.c_kind = SRC_NONE;
-  g.Cin = nomat();
-  g.Cf = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
-  g.C = nomat();
-  g.alpha = 1.0;
-  g.ctl.skip = nullptr;
-  return g;
-}
-
 }  // namespace
 
 void Engine::local_dos(const rgf_device& d, z64* store, double* twos, double* dos, double* ados_l, double* ados_r,
@@ -198,7 +181,7 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
         launch_axpy(mref(Bm, Mp, MM_), mref(sig_s, Mp, MM_), -1.0, Mp, Mp, B_, none, st_);
       }
     } else {
-      GemmArgs g = product(Mp, B_);
+      GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
       g.a_kind = SRC_FORM;
       g.Af = Aup(p);
       g.B = mref(Xm, Mp, MM_);
@@ -255,14 +238,14 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
   auto s_up = [&](int p) { return std::make_pair(d.Su + cpl(p) * M2, !fwd); };
   auto s_dn = [&](int p) { return std::make_pair(d.Su + cpl(p) * M2, fwd); };
   auto injected = [&](int q) {  // rho^s of pass layer q, from G_{q-1,0}, G_{q,0}, G_{q+1,0}
-    GemmArgs g = product(Mp, B_);
+    GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
     g.A = col(q);
     g.B = mref(gam_s, Mp, MM_);
     g.C = mref(Xb, Mp, MM_);
     gemm(g, PREC_F64, true);
     bool first = true;
     auto add = [&](FormRef s, MatRef c) {
-      GemmArgs w = product(Mp, B_);
+      GemmArgs w = gemm_args(Mp, Mp, Mp, B_);
       w.a_kind = SRC_FORM;
       w.Af = s;
       w.B = c;
@@ -300,13 +283,13 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
   for (int p = 1; p < N; ++p) {
     const MatRef gE = kept(p);
     if (dos) {  // G_{p,p-1} = -gE_p (D_p G_{p-1,p-1})
-      GemmArgs g = product(Mp, B_);
+      GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
       g.a_kind = SRC_FORM;
       g.Af = Adn(p - 1);
       g.B = gprev;
       g.C = mref(Yb, Mp, MM_);
       gemm(g, PREC_F64, true);
-      g = product(Mp, B_);
+      g = gemm_args(Mp, Mp, Mp, B_);
       g.A = gE;
       g.B = mref(Yb, Mp, MM_);
       g.C = mref(Gl, Mp, MM_);
@@ -314,13 +297,13 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
       gemm(g, PREC_F64, true);
     }
     {  // G_{p,0} = -gE_p (D_p G_{p-1,0})
-      GemmArgs g = product(Mp, B_);
+      GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
       g.a_kind = SRC_FORM;
       g.Af = Adn(p - 1);
       g.B = col(p - 1);
       g.C = mref(Yb, Mp, MM_);
       gemm(g, PREC_F64, true);
-      g = product(Mp, B_);
+      g = gemm_args(Mp, Mp, Mp, B_);
       g.A = gE;
       g.B = mref(Yb, Mp, MM_);
       g.C = mref(ring[p % 3], Mp, MM_);
@@ -329,19 +312,19 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
     }
     if (dos) {
       // V = C_{p-1} gE_p; G_{p-1,p} = -G_{p-1,p-1} V; G_pp = gE_p - G_{p,p-1} V
-      GemmArgs g = product(Mp, B_);
+      GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
       g.a_kind = SRC_FORM;
       g.Af = Aup(p - 1);
       g.B = gE;
       g.C = mref(Vb, Mp, MM_);
       gemm(g, PREC_F64, true);
-      g = product(Mp, B_);
+      g = gemm_args(Mp, Mp, Mp, B_);
       g.A = gprev;
       g.B = mref(Vb, Mp, MM_);
       g.C = mref(Gu, Mp, MM_);
       g.alpha = -1.0;
       gemm(g, PREC_F64, true);
-      g = product(Mp, B_);
+      g = gemm_args(Mp, Mp, Mp, B_);
       g.A = mref(Gl, Mp, MM_);
       g.B = mref(Vb, Mp, MM_);
       g.c_kind = SRC_MAT;

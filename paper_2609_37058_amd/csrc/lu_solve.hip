@@ -18,44 +18,16 @@
 
 namespace rgf {
 
-namespace {
-GemmArgs base_args(int rows, int cols, int K, int batch, const int32_t* skip) {
-  GemmArgs g;
-  g.rows = rows;
-  g.cols = cols;
-  g.K = K;
-  g.batch = batch;
-  g.a_kind = SRC_MAT;
-  g.A = nomat();
-  g.Af = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
-  g.B = nomat();
-  g.c_kind = SRC_NONE;
-  g.Cin = nomat();
-  g.Cf = g.Af;
-  g.C = nomat();
-  g.alpha = 1.0;
-  g.ctl.skip = skip;
-  return g;
-}
-}  // namespace
 
 void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int32_t* skip, int32_t code,
                int prec, int tile, hipStream_t st) {
   const int64_t inv_bs = (int64_t)64 * Mp;
   {  // every row starts as a pivot candidate
-    FillArgs f;
-    f.dst = nomat();
-    f.rows = 0;
-    f.cols = 0;
-    f.kind = FILL_ZERO;
+    FillArgs f = fill_args(nomat(), 0, 0, FILL_ZERO);
     f.scale = 0.0;
-    f.src = nomat();
-    f.f = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
     f.flags = g.flags;
     f.flags_bs = Mp;
     f.flags_n = Mp;
-    f.ridx = nullptr;
-    f.ridx_bs = 0;
     f.ctl.skip = skip;
     launch_fill(f, batch, st);
   }
@@ -80,13 +52,13 @@ void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int
     const int rest = Mp - k0 - LU_NB;
     if (rest <= 0) continue;
     // U12 = L11^-1 B[piv, rest], in place (one row tile: each workgroup owns its columns)
-    GemmArgs u = base_args(LU_NB, rest, LU_NB, batch, skip);
+    GemmArgs u = gemm_args(LU_NB, rest, LU_NB, batch, skip);
     u.A = mat(g.linv + (int64_t)(k0 / LU_NB) * 64 * 64, inv_bs, 64);
     u.B = mat(T + k0 + LU_NB, bs, Mp, g.perm + k0, Mp);
     u.C = u.B;
     launch_gemm(u, prec, tile, st, 0);
     // B[cand, rest] -= B[cand, K] U12
-    GemmArgs t = base_args(rest, rest, LU_NB, batch, skip);
+    GemmArgs t = gemm_args(rest, rest, LU_NB, batch, skip);
     t.A = mat(T + k0, bs, Mp, g.cand, Mp);
     t.B = mat(T + k0 + LU_NB, bs, Mp, g.perm + k0, Mp);
     t.c_kind = SRC_MAT;
@@ -133,7 +105,7 @@ void lu_solve(const LuBufs& g, z64* T, int64_t bs, int Mp, z64* Y, int64_t ybs, 
   // 128-row tiles, then the 2 x 2 block triangle with 64-row products.
   const int64_t inv_bs = (int64_t)64 * Mp;
   const int np = Mp / LU_NB;
-  const GemmArgs base = base_args(LU_NB, nrhs, LU_NB, batch, skip);
+  const GemmArgs base = gemm_args(LU_NB, nrhs, LU_NB, batch, skip);
   auto Yr = [&](int panel) { return Y + (int64_t)panel * LU_NB * nrhs; };
   auto Lrows = [&](int panel, int col0) { return mat(T + col0, bs, Mp, g.perm + panel * LU_NB, Mp); };
   auto Linv = [&](int panel) { return g.linv + (int64_t)panel * 64 * 64; };
