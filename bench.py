@@ -41,11 +41,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="block-product tile (64/128); 0 = library default")
-    ap.add_argument("--workload", choices=["c4", "bias", "kmesh", "ldos", "kpm"], default="c4",
+    ap.add_argument("--workload", choices=["c4", "bias", "kmesh", "ldos", "kpm", "serve"], default="c4",
                     help="c4: the headline zero-bias workload; bias: the C4 device at finite bias with the "
                          "Landauer current; kmesh: a transversely periodic C2-type device on a 7x7 k-mesh; "
                          "ldos: orbital-resolved LDOS and both injected parts of the C3 device; "
-                         "kpm: Chebyshev moments and the Fermi level of the C4 central region")
+                         "kpm: Chebyshev moments and the Fermi level of the C4 central region; "
+                         "serve: a C5-type request stream through the serving loop (p50/p99 latency)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (read once, written once), three "
                          "times, and exit: the reference kernel that scales the HBM byte counters")
@@ -153,6 +154,81 @@ def _timed_steps(step, steps: int, warmup: int):
         lat.append(time.perf_counter() - s0)
         print(f"[bench] step {k}: {lat[-1]:.2f} s", file=sys.stderr, flush=True)
     return time.perf_counter() - t0, lat, out
+
+
+def run_serving(args) -> int:
+    """C5-type serving mix, reduced to bench size: 24 requests, M in {128, 256, 512, 1024},
+    N ~ U[20, 60], nE ~ U[64, 256] from the common 1024-point grid, one lead type per M class.
+    A closed-loop pass (all requests at once) measures the capacity; the timed pass replays the
+    Poisson arrivals at 0.7 x that capacity and reports throughput and p50/p99 latency."""
+    import numpy as np
+    import synth
+    from paper_2609_37058_amd import rgf
+
+    n_req = 24
+    print(f"[bench] generating {n_req} requests", file=sys.stderr, flush=True)
+    reqs = synth.c5_requests(n_req=n_req, qps=1.0, n_layers=(20, 60), n_e=(64, 256))
+    blocks = []
+    for r in reqs:
+        hd, hu, sd, su = r.device.stacked()
+        L = r.device.left
+        blocks.append((hd, hu, sd, su, (L.H00, L.H01, L.S00, L.S01)))
+    work = sum(len(r.energies) * r.device.N for r in reqs)
+    eta = 1e-6
+
+    def run(arrival_scale):
+        lat, done = {}, 0
+        with rgf.Server(lead_cache_bytes=8 << 30, max_slots=4) as srv:
+            t0 = time.perf_counter()
+            tickets = {}
+            pending = sorted(range(n_req), key=lambda i: reqs[i].arrival_s)
+            while done < n_req:
+                now = time.perf_counter() - t0
+                while pending and reqs[pending[0]].arrival_s * arrival_scale <= now:
+                    i = pending.pop(0)
+                    hd, hu, sd, su, lead = blocks[i]
+                    tickets[srv.submit(hd, hu, sd, su, lead, lead, reqs[i].energies, eta,
+                                       lead_key_L=reqs[i].lead_key, lead_key_R=reqs[i].lead_key)] = i
+                for t in list(tickets):
+                    res = srv.poll(t)
+                    if res is not None:
+                        lat[tickets.pop(t)] = res[2]
+                        done += 1
+                        print(f"[bench] request {done}/{n_req} done", file=sys.stderr, flush=True)
+                time.sleep(0.002)
+            wall = time.perf_counter() - t0
+            stats = srv.stats()
+        return wall, np.array([lat[i] for i in range(n_req)]), stats
+
+    rgf.load()
+    wall0, _, _ = run(0.0)  # closed loop: every request at t = 0
+    capacity = n_req / wall0
+    scale = 1.0 / (0.7 * capacity)  # the mix's arrivals are drawn at 1 request/s
+    rgf.profile(True)
+    rgf.profile_read()
+    wall, lat, stats = run(scale)
+    n_launch, k_ms, k_flops = rgf.profile_read()
+    rgf.profile(False)
+    achieved = (k_flops / (k_ms / 1e3) / 1e12) if k_ms > 0 else None
+    out = {
+        "metric": "RGF serving: energy-point*layers/s and p50/p99 request latency (serving form)",
+        "value": work / wall, "unit": "energy-point*layers/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "c5-reduced", "requests": n_req, "block_sizes": [128, 256, 512, 1024],
+                   "layers": [20, 60], "energies": [64, 256], "arrivals": "Poisson at 0.7 x capacity",
+                   "capacity_req_per_s": capacity, "max_slots": 4, "precision": "fp64"},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+        "requests_per_s": n_req / wall,
+        "roofline": {"bound": "mfma", "kernel": "sweep block product (zgemm role 1)", "achieved": achieved,
+                     "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": (achieved / FP64_MFMA_PEAK_TFLOPS) if achieved else None, "traffic": None,
+                     "launches": n_launch, "avg_launch_ms": k_ms / max(1, n_launch)},
+        "server_stats": stats,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def run_extra_workload(args) -> int:
@@ -273,6 +349,11 @@ def main():
     args = parse()
     if args.copy_probe_mib:
         return copy_probe(args.copy_probe_mib)
+    if args.workload == "serve":
+        if args.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            return 2
+        return run_serving(args)
     if args.workload != "c4":
         return run_extra_workload(args)
     if args.gpus != 1:
