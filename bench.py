@@ -107,10 +107,14 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "zgemm_sweep_c4_fp64_traffic.tx
 
 
 def source_digest() -> str:
-    """Digest of the block-product source the HBM counters were taken on."""
+    """Digest of the sources the HBM counters were taken on: the block-product kernel and the
+    sweep driver that picks its operand forms."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2609_37058_amd", "csrc", "gemm.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("gemm.hip", "engine.hip"):
+        with open(os.path.join(ROOT, "paper_2609_37058_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -130,7 +134,7 @@ def measured_traffic():
                 k, v = line[2:].split(":", 1)
                 kv[k.strip()] = v.strip().strip("`")
     try:
-        if kv["gemm.hip sha256 prefix"] != source_digest():
+        if kv["gemm.hip + engine.hip sha256 prefix"] != source_digest():
             return None
         fetch = float(kv["sweep product FETCH_SIZE KiB/launch"]) * 1024 * float(kv["FETCH_SIZE scale"])
         write = float(kv["sweep product WRITE_SIZE KiB/launch"]) * 1024 * float(kv["WRITE_SIZE scale"])

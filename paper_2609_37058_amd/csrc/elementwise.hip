@@ -39,6 +39,42 @@ __global__ __launch_bounds__(ET) void fill_kernel(FillArgs a) {
   a.dst.p[mat_off(a.dst, b, r, c)] = v;
 }
 
+// Stored adjoint operand: dst[b] = z_b S^+ - H^+ over the padded Mp x Mp block,
+// with the zero (or identity) padding of a formed operand.  One workgroup
+// stages a 32 x 32 tile of S and H through LDS (reading rows, writing the
+// transposed rows, both coalesced) and writes it for `per` consecutive
+// batch entries, reloading only when the group's blocks change.
+constexpr int FT = 32;
+
+__global__ __launch_bounds__(ET) void form_ct_kernel(FormRef f, MatRef dst, int batch, int per) {
+  __shared__ z64 ss[FT][FT + 1], sh[FT][FT + 1];
+  const int r0 = blockIdx.x * FT, c0 = blockIdx.y * FT;
+  const int tx = threadIdx.x % FT, ty = threadIdx.x / FT;
+  const int b0 = blockIdx.z * per, b1 = min(batch, b0 + per);
+  int64_t loaded = -1;
+  for (int b = b0; b < b1; ++b) {
+    const int64_t g = form_group_off(f, b);
+    if (g != loaded) {  // uniform over the workgroup
+      __syncthreads();
+      for (int j = 0; j < FT; j += ET / FT) {
+        const int sr = c0 + ty + j, sc = r0 + tx;  // source (sr, sc) is output (sc, sr)
+        const bool ok = sr < f.M && sc < f.M;
+        ss[ty + j][tx] = ok ? f.S[g + (int64_t)sr * f.M + sc] : zmake(0.0, 0.0);
+        sh[ty + j][tx] = ok ? f.H[g + (int64_t)sr * f.M + sc] : zmake(0.0, 0.0);
+      }
+      __syncthreads();
+      loaded = g;
+    }
+    const z64 z = zmake(f.E[b], f.eta);
+    for (int j = 0; j < FT; j += ET / FT) {
+      const int r = r0 + ty + j, c = c0 + tx;
+      const z64 v = (r < f.M && c < f.M) ? zform(z, zconj(ss[tx][ty + j]), zconj(sh[tx][ty + j]))
+                                         : zmake((f.pad_identity && r == c) ? 1.0 : 0.0, 0.0);
+      dst.p[mat_off(dst, b, r, c)] = v;
+    }
+  }
+}
+
 __global__ __launch_bounds__(ET) void axpy_kernel(MatRef dst, MatRef src, double s, int rows, int cols,
                                                    BatchCtl ctl) {
   const int b = blockIdx.y;
@@ -306,6 +342,15 @@ void launch_fill(const FillArgs& a, int batch, hipStream_t st) {
   if (batch <= 0) return;
   const int64_t n = std::max<int64_t>((int64_t)a.rows * a.cols, a.flags ? a.flags_n : 0);
   hipLaunchKernelGGL(fill_kernel, dim3(nblocks(n), batch), dim3(ET), 0, st, a);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_form_ct(const FormRef& f, MatRef dst, int Mp, int batch, hipStream_t st) {
+  if (batch <= 0) return;
+  RGF_CHECK(Mp % FT == 0 && f.M <= Mp && !f.sub.p && !dst.rowidx, RGF_EINVAL, "form_ct: bad operand");
+  const int per = 8;
+  const dim3 grid((unsigned)(Mp / FT), (unsigned)(Mp / FT), (unsigned)((batch + per - 1) / per));
+  hipLaunchKernelGGL(form_ct_kernel, grid, dim3(ET), 0, st, f, dst, batch, per);
   RGF_HIP(hipGetLastError());
 }
 

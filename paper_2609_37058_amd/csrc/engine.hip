@@ -271,10 +271,13 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
       gemm(g, sp, true);
       std::swap(Wcur, Wnxt);
     }
-    // B_{l+1} = A_{l+1} - L_{l+1} X (- Sigma_R on the last layer)
+    // B_{l+1} = A_{l+1} - L_{l+1} X (- Sigma_R on the last layer).  L_{l+1} = z S_u^+ - H_u^+
+    // is stored per energy first (Z1 is free until the end of the sweep): formed inside the
+    // product, its two shared-block loads per element cost more than the extra pass.
+    launch_form_ct(gform(form(d.Hu + l * M2, d.Su + l * M2, M_, true, false, E_, eta_)), mref(Z1_, Mp, MM_), Mp,
+                   B_, st_);
     GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
-    g.a_kind = SRC_FORM;
-    g.Af = gform(form(d.Hu + l * M2, d.Su + l * M2, M_, true, false, E_, eta_));
+    g.A = mref(Z1_, Mp, MM_);
     g.B = X;
     g.c_kind = SRC_FORM;
     g.Cf = gform(form(d.Hd + (l + 1) * M2, d.Sd + (l + 1) * M2, M_, false, true, E_, eta_));

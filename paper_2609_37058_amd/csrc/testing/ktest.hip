@@ -202,4 +202,66 @@ int rgf_ktest_lu_time(int prec, int Mp, int nrhs, int batch, int reps, double* m
   });
 }
 
+// Average duration (ms) of one sweep-layer block product on Mp x Mp blocks, `batch` energies,
+// with the operand forms the sweep uses.  variant 0: W' = -W X (both operands stored);
+// 1: B' = A_ii - L X with L = z S^+ - H^+ and A_ii = z S - H formed from shared blocks;
+// 2: as 1 with L stored; 3: as 1 with L formed untransposed (z S - H); 4: -L X, L formed
+// transposed, no C operand; 5: L stored by the adjoint-formation kernel, then as 2 (both timed).
+int rgf_ktest_sweep_time(int prec, int variant, int Mp, int batch, int reps, double* ms) {
+  return kt_guard([&] {
+    RGF_CHECK(variant >= 0 && variant <= 5 && Mp % 64 == 0 && batch > 0, RGF_EINVAL, "ktest: bad sweep case");
+    const int64_t bs = (int64_t)Mp * Mp, n = bs * batch;
+    z64 *S, *H, *A, *X, *Cm;
+    double* E;
+    RGF_HIP(hipMalloc((void**)&S, sizeof(z64) * bs));
+    RGF_HIP(hipMalloc((void**)&H, sizeof(z64) * bs));
+    RGF_HIP(hipMalloc((void**)&A, sizeof(z64) * n));
+    RGF_HIP(hipMalloc((void**)&X, sizeof(z64) * n));
+    RGF_HIP(hipMalloc((void**)&Cm, sizeof(z64) * n));
+    RGF_HIP(hipMalloc((void**)&E, sizeof(double) * batch));
+    kt_random(S, bs, Mp, Mp, 4.0);
+    kt_random(H, bs, Mp, Mp, 0.0);
+    kt_random(A, n, Mp, Mp, 0.0);
+    kt_random(X, n, Mp, Mp, 0.0);
+    std::vector<double> eh(batch);
+    for (int b = 0; b < batch; ++b) eh[b] = -1.0 + 2.0 * b / batch;
+    RGF_HIP(hipMemcpy(E, eh.data(), sizeof(double) * batch, hipMemcpyHostToDevice));
+    GemmArgs g = gemm_args(Mp, Mp, Mp, batch);
+    g.B = mat(X, bs, Mp);
+    g.C = mat(Cm, bs, Mp);
+    g.alpha = -1.0;
+    const FormRef lf = form(reinterpret_cast<const rgf_z*>(H), reinterpret_cast<const rgf_z*>(S), Mp, true,
+                            false, E, 1e-6);
+    if (variant == 0 || variant == 2 || variant == 5) {
+      g.A = mat(A, bs, Mp);
+    } else {
+      g.a_kind = SRC_FORM;
+      g.Af = form(reinterpret_cast<const rgf_z*>(H), reinterpret_cast<const rgf_z*>(S), Mp, variant != 3,
+                  false, E, 1e-6);
+    }
+    if (variant >= 1 && variant != 4) {
+      g.c_kind = SRC_FORM;
+      g.Cf = form(reinterpret_cast<const rgf_z*>(H), reinterpret_cast<const rgf_z*>(S), Mp, false, true, E, 1e-6);
+    }
+    hipEvent_t e0, e1;
+    RGF_HIP(hipEventCreate(&e0));
+    RGF_HIP(hipEventCreate(&e1));
+    if (variant == 5) launch_form_ct(lf, mat(A, bs, Mp), Mp, batch, nullptr);
+    launch_gemm(g, prec, 128, nullptr, 1);
+    RGF_HIP(hipEventRecord(e0, nullptr));
+    for (int r = 0; r < reps; ++r) {
+      if (variant == 5) launch_form_ct(lf, mat(A, bs, Mp), Mp, batch, nullptr);
+      launch_gemm(g, prec, 128, nullptr, 1);
+    }
+    RGF_HIP(hipEventRecord(e1, nullptr));
+    RGF_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    RGF_HIP(hipEventElapsedTime(&t, e0, e1));
+    *ms = t / reps;
+    RGF_HIP(hipEventDestroy(e0));
+    RGF_HIP(hipEventDestroy(e1));
+    for (void* q : {(void*)S, (void*)H, (void*)A, (void*)X, (void*)Cm, (void*)E}) RGF_HIP(hipFree(q));
+  });
+}
+
 }  // extern "C"

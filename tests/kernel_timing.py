@@ -4,7 +4,9 @@ Runs the test-only kernel harness librgf_ktest.so (built by build()) on the
 shapes that make up one layer of the C4 sweep (Mp = 1024, 64 energies per
 launch) and on the skinny products of the KPM solve sweeps, and prints
 microseconds and TFLOP/s per shape (8 real flops per complex multiply-add).
-Usage: python tests/kernel_timing.py [--only-product]
+With --sweep-variants it times the two sweep products with the operand forms
+the sweep uses (formed, adjoint-formed or stored), FP64 and FP32.
+Usage: python tests/kernel_timing.py [--only-product | --sweep-variants]
 """
 import ctypes as C
 import os
@@ -30,8 +32,21 @@ def main():
     lib = C.CDLL(os.path.join(ROOT, "paper_2609_37058_amd", "librgf_ktest.so"))
     lib.rgf_ktest_gemm_time.argtypes = [C.c_int] * 8 + [C.POINTER(C.c_double)]
     lib.rgf_ktest_lu_time.argtypes = [C.c_int] * 5 + [C.POINTER(C.c_double)] * 2
+    lib.rgf_ktest_sweep_time.argtypes = [C.c_int] * 5 + [C.POINTER(C.c_double)]
     torch.cuda.init()
     ms = C.c_double()
+    if "--sweep-variants" in sys.argv:
+        names = ["W' = -W X, stored operands", "B' = A - L X, L adjoint-formed, A formed",
+                 "B' with L stored, A formed", "B' with L formed untransposed", "-L X, L adjoint-formed, no C",
+                 "adjoint formation kernel + B' with L stored"]
+        cases = [(Mp, nb, prec, v) for Mp, nb in ((1024, 64), (512, 64), (256, 128)) for prec in (0, 1)
+                 for v in range(len(names)) if Mp == 1024 or v in (0, 1, 5)]
+        for Mp, nb, prec, v in cases:
+            rc = lib.rgf_ktest_sweep_time(prec, v, Mp, nb, 5, C.byref(ms))
+            fl = 8.0 * Mp ** 3 * nb
+            print(f"| Mp={Mp} x {nb} | {'FP64' if prec == 0 else 'FP32'} | {names[v]} | {ms.value:.3f} ms | "
+                  f"{fl / ms.value / 1e9:.1f} TFLOP/s | rc={rc}", flush=True)
+        return
     shapes = SHAPES[5:6] if "--only-product" in sys.argv else SHAPES
     for tile, rows, cols, K, batch, inplace, label in shapes:
         rc = lib.rgf_ktest_gemm_time(0, tile, rows, cols, K, batch, inplace, 5, C.byref(ms))
