@@ -198,7 +198,8 @@ int rgf_transmission_kmesh(const rgf_device* images, int32_t nR, const int32_t* 
  * pointers, row-major; any of the three may be NULL (not all).  info[nE]
  * (DEVICE, may be NULL) as in rgf_transmission.  FP64 only.  The library keeps
  * N padded M x M blocks per energy in its workspace (N Mp^2 x 16 bytes, Mp =
- * M rounded up to 64), so energies run in chunks that fit 80% of free HBM.
+ * M rounded up to 64) and three padded overlap blocks per energy lane, so
+ * energies run in chunks that fit 80% of free HBM.
  * Stream-ordered; RGF_EINVAL as rgf_transmission and when no output is given.
  */
 int rgf_ldos(const rgf_device* dev, const double* E, int64_t nE, double eta, double* dos, double* ados_left,
@@ -218,8 +219,9 @@ int rgf_ldos(const rgf_device* dev, const double* E, int64_t nE, double eta, dou
  * for n < n_mom (DEVICE array of doubles).  [e_min, e_max] must enclose the
  * spectrum of (H, S).  S is factored once per call (block Thomas, FP64;
  * RGF_EINVAL if a pivot is exactly zero).  The library keeps 3 N Mp^2 complex
- * factors and 5 N Mp Rp complex vector panels (Mp, Rp = M, R rounded up to
- * 64) in a workspace per stream.  Stream-ordered (blocks for the S check);
+ * factors, the 3 N Mp^2 complex blocks of b S - H and 5 N Mp Rp complex
+ * vector panels (Mp, Rp = M, R rounded up to 64) in a workspace per stream
+ * (RGF_ENOMEM when it does not fit).  Stream-ordered (blocks for the S check);
  * RGF_EINVAL for null pointers, N < 1, M outside [1, 2048], n_mom < 1, R < 1
  * or bad bounds.
  */

@@ -578,6 +578,9 @@ static int64_t ldos_chunk(int Mp, int N, int64_t nE, double share) {
   if (const char* s = std::getenv("RGF_MEM_FRACTION")) frac = std::atof(s);
   const size_t per =
       Layout::make(Mp, 1).bytes + sizeof(z64) * (size_t)N * Mp * Mp + 2 * sizeof(double) + 512;
+  // each lane's three shared overlap blocks
+  const size_t fixed = (size_t)((double)(sizeof(z64) * 3 * (size_t)Mp * Mp) / share);
+  fr = fr > fixed ? fr - fixed : 0;
   int64_t chunk = std::max<int64_t>(1, (int64_t)(frac * share * (double)fr / (double)per));
   if (const char* s = std::getenv("RGF_MAX_CHUNK")) chunk = std::min<int64_t>(chunk, std::max(1, std::atoi(s)));
   return std::min<int64_t>(std::min<int64_t>(chunk, nE), 65535);
@@ -598,7 +601,8 @@ static void ldos_range(const rgf_device& d, const double* E, int64_t lo, int64_t
     const Layout lay = Layout::make(Mp, B);
     const size_t store_off = round_up((int64_t)lay.bytes, 256);
     const size_t twos_off = store_off + round_up((int64_t)(sizeof(z64) * (size_t)B * N * MM), 256);
-    Workspace& w = workspace(dev, st, twos_off + sizeof(double) * B);
+    const size_t sblk_off = twos_off + round_up((int64_t)(sizeof(double) * B), 256);
+    Workspace& w = workspace(dev, st, sblk_off + sizeof(z64) * 3 * MM);
     Engine eng(w.base, lay, st, PREC_F64, M, E + e0, eta, w.host_active);
     eng.decimate(d.left, eng.done_l(), true);
     eng.self_energy(d.left, true, eng.sigL());
@@ -606,6 +610,7 @@ static void ldos_range(const rgf_device& d, const double* E, int64_t lo, int64_t
     eng.self_energy(d.right, false, eng.sigR());
     eng.broadenings();
     eng.local_dos(d, reinterpret_cast<z64*>(w.base + store_off), reinterpret_cast<double*>(w.base + twos_off),
+                  reinterpret_cast<z64*>(w.base + sblk_off),
                   dos ? dos + e0 * out_per : nullptr, ados_l ? ados_l + e0 * out_per : nullptr,
                   ados_r ? ados_r + e0 * out_per : nullptr, info ? info + e0 : nullptr, same);
     e0 += B;

@@ -67,9 +67,10 @@ class Engine {
   void sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool same_leads);
   // orbital-resolved LDOS and the electrode-injected parts, each [batch][N][M]
   // (any may be null), after the self-energies and broadenings; `store` holds
-  // N Mp^2 per energy (batch stride N Mp^2), `twos` one double per energy
-  void local_dos(const rgf_device& d, z64* store, double* twos, double* dos, double* ados_l, double* ados_r,
-                 int32_t* info, bool same_leads);
+  // N Mp^2 per energy (batch stride N Mp^2), `twos` one double per energy,
+  // `sblk` three Mp^2 blocks shared by all energies (overlap operands)
+  void local_dos(const rgf_device& d, z64* store, double* twos, z64* sblk, double* dos, double* ados_l,
+                 double* ados_r, int32_t* info, bool same_leads);
   // lead-only output: copy sigma into the caller's dense [batch][M][M]
   void export_sigma(z64* sigma_ws, rgf_z* out);
   void lead_info(int side_bit, int32_t* done, int32_t* info);
@@ -85,7 +86,10 @@ class Engine {
  private:
   MatRef mref(z64* p, int64_t ld, int64_t bstride, const int32_t* ridx = nullptr) const;
   double gemm(GemmArgs g, int prec, bool timed);
-  void ldos_pass(const rgf_device& d, z64* store, const double* twos, bool forward, double* dos, double* inj);
+  void ldos_pass(const rgf_device& d, z64* store, const double* twos, z64* sblk, bool forward, double* dos,
+                 double* inj);
+  // dst (Mp x Mp per batch entry, batch stride Mp^2) = the formed operand f for `batch` entries
+  MatRef store_form(const FormRef& f, z64* dst, int batch);
   FormRef gform(FormRef f) const {
     f.gper = gper_;
     f.gb0 = gb0_;

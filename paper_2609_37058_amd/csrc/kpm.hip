@@ -236,6 +236,9 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
   };
   const size_t o_dinv = take(sizeof(z64) * N * MM), o_uf = take(sizeof(z64) * N * MM),
                o_lf = take(sizeof(z64) * N * MM), o_t = take(sizeof(z64) * MM);
+  // b S - H blocks (diagonal, upper, lower), formed once: every Chebyshev step reads them
+  const size_t o_ad = take(sizeof(z64) * N * MM), o_au = take(sizeof(z64) * N * MM),
+               o_al = take(sizeof(z64) * N * MM);
   size_t o_v[5];
   for (int i = 0; i < 5; ++i) o_v[i] = take(sizeof(z64) * VN);
   const size_t o_linv = take(sizeof(z64) * 64 * Mp), o_uinv = take(sizeof(z64) * 64 * Mp);
@@ -266,6 +269,9 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
   z64* Uf = reinterpret_cast<z64*>(base + o_uf);
   z64* Lf = reinterpret_cast<z64*>(base + o_lf);
   z64* T = reinterpret_cast<z64*>(base + o_t);
+  z64* Ad = reinterpret_cast<z64*>(base + o_ad);
+  z64* Au = reinterpret_cast<z64*>(base + o_au);
+  z64* Al = reinterpret_cast<z64*>(base + o_al);
   z64* V[5];
   for (int i = 0; i < 5; ++i) V[i] = reinterpret_cast<z64*>(base + o_v[i]);
   LuBufs lu;
@@ -357,28 +363,37 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
     f.gstride = M2;
     return f;
   };
+  {  // the operator's blocks, one per batch entry (= layer)
+    FillArgs f = fill_args(mat(Ad, MM, Mp), Mp, Mp, FILL_FORM);
+    f.f = grouped(form(d.Hd, d.Sd, M, false, false, bvals, 0.0));
+    launch_fill(f, N, st);
+    if (N > 1) {
+      f = fill_args(mat(Au, MM, Mp), Mp, Mp, FILL_FORM);
+      f.f = grouped(form(d.Hu, d.Su, M, false, false, bvals, 0.0));
+      launch_fill(f, N - 1, st);
+      launch_form_ct(grouped(form(d.Hu, d.Su, M, true, false, bvals, 0.0)), mat(Al, MM, Mp), Mp, N - 1, st);
+    }
+  }
   for (int n = 0; n + 1 < n_mom; ++n) {
     z64* X = ring[n % 3];
     const double alpha = (n == 0 ? -1.0 : -2.0) / a;  // c (H - b S) / a = -(c / a) (b S - H)
     // W = c (H - b S) V / a: diagonal, upper and lower blocks
     GemmArgs g = gemm_args(Mp, Rp, Mp, N);
-    g.a_kind = SRC_FORM;
-    g.Af = grouped(form(d.Hd, d.Sd, M, false, false, bvals, 0.0));
+    g.A = mat(Ad, MM, Mp);
     g.B = panel(vcur, 0);
     g.C = panel(W, 0);
     g.alpha = alpha;
     timed_gemm(g, st);
     if (N > 1) {
       g = gemm_args(Mp, Rp, Mp, N - 1);
-      g.a_kind = SRC_FORM;
-      g.Af = grouped(form(d.Hu, d.Su, M, false, false, bvals, 0.0));
+      g.A = mat(Au, MM, Mp);
       g.B = panel(vcur, 1);
       g.c_kind = SRC_MAT;
       g.Cin = panel(W, 0);
       g.C = panel(W, 0);
       g.alpha = alpha;
       timed_gemm(g, st);
-      g.Af = grouped(form(d.Hu, d.Su, M, true, false, bvals, 0.0));
+      g.A = mat(Al, MM, Mp);
       g.B = panel(vcur, 0);
       g.Cin = panel(W, 1);
       g.C = panel(W, 1);

@@ -26,8 +26,11 @@
 //   [A S]_pp[mu]   = -Im sum_q ( rowsum(G_pq .* conj S_pq)[mu] + colsum(G_qp .* conj S_qp)[mu] ),
 //   [A_s S]_pp[mu] = Re rowsum(X_p .* conj W_p)[mu],
 //   X_p = G_{p,0} Gamma_s,  W_p = sum_q S_pq G_{q,0}   (q = p-1, p, p+1).
-// The overlap-only operands S_pq are formed from the shared blocks as
-// z S - H with H = S and z = 2 (exact in binary floating point).
+// The energy-dependent couplings C_p, D_p are written per energy before their
+// products (a formed operand costs the product two block loads per element);
+// the overlap-only operands S_pq are written once per layer as padded blocks
+// shared by all energies, formed as z S - H with H = S and z = 2 (exact in
+// binary floating point).
 #include <utility>
 
 #include "engine.h"
@@ -121,20 +124,32 @@ void launch_proj(const ProjArgs& a, bool rows, int batch, hipStream_t st) {
 
 }  // namespace
 
-void Engine::local_dos(const rgf_device& d, z64* store, double* twos, double* dos, double* ados_l, double* ados_r,
-                       int32_t* info, bool same_leads) {
+MatRef Engine::store_form(const FormRef& f, z64* dst, int batch) {
+  if (f.conj_t) {
+    launch_form_ct(f, mref(dst, Mp_, MM_), Mp_, batch, st_);
+  } else {
+    FillArgs a = fill_args(mref(dst, Mp_, MM_), Mp_, Mp_, FILL_FORM);
+    a.f = f;
+    launch_fill(a, batch, st_);
+  }
+  return mref(dst, Mp_, MM_);
+}
+
+void Engine::local_dos(const rgf_device& d, z64* store, double* twos, z64* sblk, double* dos, double* ados_l,
+                       double* ados_r, int32_t* info, bool same_leads) {
   hipLaunchKernelGGL(fill_value_kernel, dim3((B_ + 255) / 256), dim3(256), 0, st_, twos, B_, 2.0);
   RGF_HIP(hipGetLastError());
   if (dos) RGF_HIP(hipMemsetAsync(dos, 0, sizeof(double) * (size_t)B_ * d.N * M_, st_));
-  if (dos || ados_l) ldos_pass(d, store, twos, true, dos, ados_l);
-  if (ados_r) ldos_pass(d, store, twos, false, nullptr, ados_r);
+  if (dos || ados_l) ldos_pass(d, store, twos, sblk, true, dos, ados_l);
+  if (ados_r) ldos_pass(d, store, twos, sblk, false, nullptr, ados_r);
   if (info) {
     launch_sr_info(done_l_, RGF_INFO_SR_LEFT, sing_, info, B_, 0, st_);
     launch_sr_info(same_leads ? done_l_ : done_r_, RGF_INFO_SR_RIGHT, sing_, info, B_, 1, st_);
   }
 }
 
-void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool fwd, double* dos, double* inj) {
+void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, z64* sblk, bool fwd, double* dos,
+                       double* inj) {
   const int Mp = Mp_, N = d.N, M = M_;
   const int64_t M2 = (int64_t)M * M;
   const int64_t SB = (int64_t)N * MM_;  // batch stride of the kept inverses
@@ -182,8 +197,7 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
       }
     } else {
       GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
-      g.a_kind = SRC_FORM;
-      g.Af = Aup(p);
+      g.A = store_form(Aup(p), work(2), B_);
       g.B = mref(Xm, Mp, MM_);
       g.c_kind = SRC_FORM;
       g.Cf = Adiag(p);
@@ -220,6 +234,7 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
   z64* Gu = work(8);
   z64* Xb = work(9);
   z64* Wb = work(10);
+  z64* Cst = work(11);  // the current coupling, stored per energy
   auto col = [&](int q) { return q == 0 ? kept(0) : mref(ring[q % 3], Mp, MM_); };
   auto proj = [&](MatRef G, const rgf_z* s, bool conj, int row_layer, int col_layer) {
     ProjArgs a;
@@ -237,6 +252,19 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
   // S_{p,p+1} and S_{p+1,p} in pass order (raw block and whether it enters as its adjoint)
   auto s_up = [&](int p) { return std::make_pair(d.Su + cpl(p) * M2, !fwd); };
   auto s_dn = [&](int p) { return std::make_pair(d.Su + cpl(p) * M2, fwd); };
+  // an overlap block as a padded Mp x Mp operand shared by every energy (slot 0..2 of sblk)
+  auto shared_s = [&](int slot, const rgf_z* s, bool conj) {
+    z64* dst = sblk + (int64_t)slot * MM_;
+    const FormRef f = Sform(s, conj);
+    if (conj) {
+      launch_form_ct(f, mat(dst, MM_, Mp), Mp, 1, st_);
+    } else {
+      FillArgs a = fill_args(mat(dst, MM_, Mp), Mp, Mp, FILL_FORM);
+      a.f = f;
+      launch_fill(a, 1, st_);
+    }
+    return mat(dst, 0, Mp);
+  };
   auto injected = [&](int q) {  // rho^s of pass layer q, from G_{q-1,0}, G_{q,0}, G_{q+1,0}
     GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
     g.A = col(q);
@@ -244,10 +272,9 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
     g.C = mref(Xb, Mp, MM_);
     gemm(g, PREC_F64, true);
     bool first = true;
-    auto add = [&](FormRef s, MatRef c) {
+    auto add = [&](MatRef s, MatRef c) {
       GemmArgs w = gemm_args(Mp, Mp, Mp, B_);
-      w.a_kind = SRC_FORM;
-      w.Af = s;
+      w.A = s;
       w.B = c;
       if (!first) {
         w.c_kind = SRC_MAT;
@@ -259,12 +286,12 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
     };
     if (q >= 1) {
       auto s = s_dn(q - 1);
-      add(Sform(s.first, s.second), col(q - 1));
+      add(shared_s(0, s.first, s.second), col(q - 1));
     }
-    add(Sform(d.Sd + layer(q) * M2, false), col(q));
+    add(shared_s(1, d.Sd + layer(q) * M2, false), col(q));
     if (q + 1 <= N - 1) {
       auto s = s_up(q);
-      add(Sform(s.first, s.second), col(q + 1));
+      add(shared_s(2, s.first, s.second), col(q + 1));
     }
     InjArgs a;
     a.X = mref(Xb, Mp, MM_);
@@ -282,10 +309,10 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
   if (dos) proj(kept(0), d.Sd + layer(0) * M2, false, layer(0), layer(0));
   for (int p = 1; p < N; ++p) {
     const MatRef gE = kept(p);
+    const MatRef Dp = store_form(Adn(p - 1), Cst, B_);
     if (dos) {  // G_{p,p-1} = -gE_p (D_p G_{p-1,p-1})
       GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
-      g.a_kind = SRC_FORM;
-      g.Af = Adn(p - 1);
+      g.A = Dp;
       g.B = gprev;
       g.C = mref(Yb, Mp, MM_);
       gemm(g, PREC_F64, true);
@@ -298,8 +325,7 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
     }
     {  // G_{p,0} = -gE_p (D_p G_{p-1,0})
       GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
-      g.a_kind = SRC_FORM;
-      g.Af = Adn(p - 1);
+      g.A = Dp;
       g.B = col(p - 1);
       g.C = mref(Yb, Mp, MM_);
       gemm(g, PREC_F64, true);
@@ -313,8 +339,7 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, bool
     if (dos) {
       // V = C_{p-1} gE_p; G_{p-1,p} = -G_{p-1,p-1} V; G_pp = gE_p - G_{p,p-1} V
       GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
-      g.a_kind = SRC_FORM;
-      g.Af = Aup(p - 1);
+      g.A = store_form(Aup(p - 1), Cst, B_);  // D_p's products are queued before this overwrite
       g.B = gE;
       g.C = mref(Vb, Mp, MM_);
       gemm(g, PREC_F64, true);
