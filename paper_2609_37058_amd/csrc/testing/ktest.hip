@@ -264,4 +264,25 @@ int rgf_ktest_sweep_time(int prec, int variant, int Mp, int batch, int reps, dou
   });
 }
 
+// The stored adjoint operand two ways: out_ct by the tiled formation kernel, out_fill by the
+// element-wise fill (the formed operand's definition), both [batch][Mp][Mp].  H, S: `groups`
+// consecutive M x M blocks; batch entry b reads group b / per (per = ceil(batch / groups)).
+int rgf_ktest_form_ct(int M, int Mp, int batch, int groups, int pad, const void* H, const void* S, const double* E,
+                      double eta, void* out_ct, void* out_fill) {
+  return kt_guard([&] {
+    RGF_CHECK(M >= 1 && Mp >= M && Mp % 64 == 0 && batch >= 1 && groups >= 1 && groups <= batch, RGF_EINVAL,
+              "ktest: bad form case");
+    FormRef f = form(reinterpret_cast<const rgf_z*>(H), reinterpret_cast<const rgf_z*>(S), M, true, pad != 0, E, eta);
+    f.gper = (batch + groups - 1) / groups;
+    f.gb0 = 0;
+    f.gstride = (int64_t)M * M;
+    const int64_t bs = (int64_t)Mp * Mp;
+    launch_form_ct(f, mat((z64*)out_ct, bs, Mp), Mp, batch, nullptr);
+    FillArgs a = fill_args(mat((z64*)out_fill, bs, Mp), Mp, Mp, FILL_FORM);
+    a.f = f;
+    launch_fill(a, batch, nullptr);
+    RGF_HIP(hipDeviceSynchronize());
+  });
+}
+
 }  // extern "C"

@@ -27,6 +27,7 @@ def kt():
                                    C.c_void_p, C.c_void_p, C.c_double, C.c_int]
     lib.rgf_ktest_lu.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p]
+    lib.rgf_ktest_form_ct.argtypes = [C.c_int] * 5 + [C.c_void_p] * 3 + [C.c_double, C.c_void_p, C.c_void_p]
     return lib
 
 
@@ -83,3 +84,34 @@ def test_lu_solve_matches_numpy_solve(kt, prec, Mp, nrhs, batch):
     assert np.all(sing == 0)
     # FP32 trailing updates and solves: the error grows with the order of these row-scaled random systems
     assert err < (1e-11 if prec == 0 else 1e-3 * max(1.0, Mp / 512))
+
+
+@pytest.mark.parametrize("M,Mp,batch,groups,pad", [(64, 64, 1, 1, 0), (100, 128, 13, 1, 0), (130, 192, 9, 3, 1),
+                                                   (1024, 1024, 3, 3, 0), (33, 64, 17, 17, 1)])
+def test_adjoint_formation_kernel(kt, M, Mp, batch, groups, pad):
+    """z_b S^+ - H^+ written by the tiled kernel equals the element-wise fill bitwise and the
+    definition (numpy) to rounding; the padding is zero (identity on the diagonal with pad)."""
+    import torch
+    rng = np.random.default_rng(M + batch)
+    H = _rand(rng, (groups, M, M))
+    S = _rand(rng, (groups, M, M))
+    E = np.linspace(-1.0, 1.0, batch)
+    eta = 1e-3
+    th, ts = torch.as_tensor(H).cuda(), torch.as_tensor(S).cuda()
+    te = torch.as_tensor(E).cuda()
+    oc = torch.full((batch, Mp, Mp), complex(7.0, 7.0), dtype=torch.complex128, device="cuda")
+    of = torch.full((batch, Mp, Mp), complex(-7.0, 7.0), dtype=torch.complex128, device="cuda")
+    rc = kt.rgf_ktest_form_ct(M, Mp, batch, groups, pad, th.data_ptr(), ts.data_ptr(), te.data_ptr(), eta,
+                              oc.data_ptr(), of.data_ptr())
+    assert rc == 0
+    oc, of = oc.cpu().numpy(), of.cpu().numpy()
+    assert np.array_equal(oc.view(np.float64), of.view(np.float64))
+    per = -(-batch // groups)
+    for b in range(batch):
+        g = b // per
+        ref = np.zeros((Mp, Mp), dtype=np.complex128)
+        if pad:
+            ref[np.arange(M, Mp), np.arange(M, Mp)] = 1.0
+        ref[:M, :M] = (E[b] + 1j * eta) * S[g].conj().T - H[g].conj().T
+        assert np.allclose(oc[b], ref, rtol=0, atol=1e-14 * (1 + np.abs(ref).max()))
+        assert np.array_equal(oc[b][M:, :], ref[M:, :]) and np.array_equal(oc[b][:, M:], ref[:, M:])
