@@ -6,7 +6,8 @@ launch) and on the skinny products of the KPM solve sweeps, and prints
 microseconds and TFLOP/s per shape (8 real flops per complex multiply-add).
 With --sweep-variants it times the two sweep products with the operand forms
 the sweep uses (formed, adjoint-formed or stored), FP64 and FP32.
-Usage: python tests/kernel_timing.py [--only-product | --sweep-variants]
+With --fp32 the shapes and the LU run on the FP32 matrix cores (the mixed form).
+Usage: python tests/kernel_timing.py [--only-product | --sweep-variants] [--fp32]
 """
 import ctypes as C
 import os
@@ -48,15 +49,16 @@ def main():
                   f"{fl / ms.value / 1e9:.1f} TFLOP/s | rc={rc}", flush=True)
         return
     shapes = SHAPES[5:6] if "--only-product" in sys.argv else SHAPES
+    prec = 1 if "--fp32" in sys.argv else 0
     for tile, rows, cols, K, batch, inplace, label in shapes:
-        rc = lib.rgf_ktest_gemm_time(0, tile, rows, cols, K, batch, inplace, 5, C.byref(ms))
+        rc = lib.rgf_ktest_gemm_time(prec, tile, rows, cols, K, batch, inplace, 5, C.byref(ms))
         fl = 8.0 * rows * cols * K * batch
         print(f"| {label} | {ms.value * 1e3:.1f} | {fl / ms.value / 1e9:.1f} | rc={rc}", flush=True)
     if "--only-product" in sys.argv:
         return
     f, s = C.c_double(), C.c_double()
     for Mp in (512, 1024):
-        rc = lib.rgf_ktest_lu_time(0, Mp, Mp, 64, 3, C.byref(f), C.byref(s))
+        rc = lib.rgf_ktest_lu_time(prec, Mp, Mp, 64, 3, C.byref(f), C.byref(s))
         print(f"LU Mp={Mp}, 64 energies: factor {f.value:.2f} ms, solves {s.value:.2f} ms rc={rc}", flush=True)
 
 
