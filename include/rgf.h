@@ -299,14 +299,17 @@ const char* rgf_version(void);
 int rgf_release_workspaces(void);
 
 /*
- * Kernel timing.  rgf_profile(1) makes later calls record a HIP event pair
- * around every launch of the dominant block-product kernel on the stream it
- * is launched on; rgf_profile_read returns the number of such launches, their
- * summed duration in milliseconds and their summed algorithmic flops (8 real
- * flops per complex multiply-add), then resets the counters.  Recording adds
- * a little overhead, so leave it off outside measurement.
+ * Kernel timing.  rgf_profile(n), n >= 1, makes later calls record a HIP event
+ * pair around every n-th launch of the dominant block-product kernel (counted
+ * over all streams from this call on) on the stream it is launched on;
+ * rgf_profile(0) stops recording.  rgf_profile_read returns the number of
+ * recorded launches, their summed duration in milliseconds and their summed
+ * algorithmic flops (8 real flops per complex multiply-add), then resets the
+ * counters.  Recording costs two event records per sampled launch, so sample
+ * (n > 1) where the launches are short and many, and leave it off outside
+ * measurement.  RGF_EINVAL for n < 0.
  */
-int rgf_profile(int enable);
+int rgf_profile(int every);
 int rgf_profile_read(int64_t* launches, double* total_ms, double* flops);
 
 /* Tile configuration of the FP64 and mixed block products: 128 (128x128 output

@@ -23,6 +23,8 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 struct Profiler {
   std::mutex mu;
   bool on = false;
+  int every = 1;       // record one launch in `every`
+  int64_t seen = 0;    // launches seen while on
   struct Rec {
     hipEvent_t a, b;
     double flops;
@@ -61,11 +63,16 @@ Profiler& profiler() { return g_prof; }
 bool profiling() { return g_prof.on; }
 void profile_launch_begin(hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (g_prof.seen++ % g_prof.every != 0) {  // not sampled
+    t_pending_begin = nullptr;
+    return;
+  }
   t_pending_begin = g_prof.get();
   RGF_HIP(hipEventRecord(t_pending_begin, st));
 }
 void profile_launch_end(hipStream_t st, double flops) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (!t_pending_begin) return;
   hipEvent_t e = g_prof.get();
   RGF_HIP(hipEventRecord(e, st));
   g_prof.recs.push_back({t_pending_begin, e, flops});
@@ -809,10 +816,13 @@ int rgf_release_workspaces(void) {
   });
 }
 
-int rgf_profile(int enable) {
+int rgf_profile(int every) {
   return guarded([&] {
+    RGF_CHECK(every >= 0, RGF_EINVAL, "rgf_profile: negative sampling period");
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    g_prof.on = enable != 0;
+    g_prof.on = every != 0;
+    g_prof.every = every > 0 ? every : 1;
+    g_prof.seen = 0;
   });
 }
 

@@ -355,8 +355,9 @@ def release_workspaces():
     _check(load().rgf_release_workspaces())
 
 
-def profile(enable: bool):
-    _check(load().rgf_profile(1 if enable else 0))
+def profile(enable: bool, every: int = 1):
+    """Record HIP events around every `every`-th launch of the dominant block product."""
+    _check(load().rgf_profile(int(every) if enable else 0))
 
 
 def profile_read() -> Tuple[int, float, float]:

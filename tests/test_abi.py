@@ -60,6 +60,8 @@ def test_argument_errors_before_device_work(lib):
     assert L.rgf_kpm_moments(None, -1.0, 1.0, 10, None, 4, None, None) == rgf.RGF_EINVAL
     assert L.rgf_kpm_fermi(None, 10, 1.0, -1.0, 3.0, None, None) == rgf.RGF_EINVAL
     assert L.rgf_kpm_dos(None, 0, -1.0, 1.0, None, 5, None, None) == rgf.RGF_EINVAL
+    assert L.rgf_profile(-1) == rgf.RGF_EINVAL
+    assert L.rgf_profile(16) == rgf.RGF_OK and L.rgf_profile(0) == rgf.RGF_OK
 
 
 def test_tuning_table_on_the_host(tmp_path):
