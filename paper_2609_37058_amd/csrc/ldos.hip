@@ -71,18 +71,29 @@ __global__ void __launch_bounds__(256) proj_rows_kernel(ProjArgs a) {
   if (lane == 0) a.out[b * a.out_bs + (int64_t)a.layer * a.M + r] -= INV_2PI * acc;
 }
 
-// out[layer][c] += -(1/2pi) Im sum_r G[r][c] conj(S[r][c]); one thread per column
-__global__ void __launch_bounds__(256) proj_cols_kernel(ProjArgs a) {
+// out[layer][c] += -(1/2pi) Im sum_r G[r][c] conj(S[r][c]); a workgroup takes 16 columns,
+// its 16 row groups stride the rows and their partial sums are added in row-group order
+constexpr int PC_COLS = 16, PC_GROUPS = 16;
+__global__ void __launch_bounds__(PC_COLS * PC_GROUPS) proj_cols_kernel(ProjArgs a) {
+  __shared__ double part[PC_GROUPS][PC_COLS];
   const int b = blockIdx.y;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.M) return;
+  const int tx = threadIdx.x % PC_COLS, ty = threadIdx.x / PC_COLS;
+  const int c = blockIdx.x * PC_COLS + tx;
   double acc = 0.0;
-  for (int r = 0; r < a.M; ++r) {
-    const z64 g = a.G.p[mat_off(a.G, b, r, c)];
-    const z64 s = s_elem(a, r, c);
-    acc += g.y * s.x - g.x * s.y;
+  if (c < a.M) {
+    for (int r = ty; r < a.M; r += PC_GROUPS) {
+      const z64 g = a.G.p[mat_off(a.G, b, r, c)];
+      const z64 s = s_elem(a, r, c);
+      acc += g.y * s.x - g.x * s.y;
+    }
   }
-  a.out[b * a.out_bs + (int64_t)a.layer * a.M + c] -= INV_2PI * acc;
+  part[ty][tx] = acc;
+  __syncthreads();
+  if (ty == 0 && c < a.M) {
+    double t = 0.0;
+    for (int k = 0; k < PC_GROUPS; ++k) t += part[k][tx];
+    a.out[b * a.out_bs + (int64_t)a.layer * a.M + c] -= INV_2PI * t;
+  }
 }
 
 struct InjArgs {
@@ -118,7 +129,8 @@ void launch_proj(const ProjArgs& a, bool rows, int batch, hipStream_t st) {
   if (rows)
     hipLaunchKernelGGL(proj_rows_kernel, dim3((a.M + 3) / 4, batch), dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL(proj_cols_kernel, dim3((a.M + 255) / 256, batch), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(proj_cols_kernel, dim3((a.M + PC_COLS - 1) / PC_COLS, batch), dim3(PC_COLS * PC_GROUPS), 0,
+                       st, a);
   RGF_HIP(hipGetLastError());
 }
 
