@@ -1,9 +1,12 @@
 // Driver of the batched blocked LU with partial pivoting and of the two
 // block triangular solves that follow it.
 //
-// Factorisation, per 64-column panel (one panel kernel, two block products):
-//   B[piv, rest]  = L11^-1 B[piv, rest]            U12, rows = 64, K = 64
-//   B[cand, rest] -= B[cand, K] B[piv, rest]       trailing update, K = 64
+// Factorisation in pairs of 64-column panels a, b (one panel kernel each):
+//   B[piv_a, b]    = La^-1 B[piv_a, b];  B[cand_a, b] -= B[cand_a, a] B[piv_a, b]
+//   panel b, then for the columns r right of the pair
+//   B[piv_a, r]    = La^-1 B[piv_a, r];  B[piv_b, r] -= B[piv_b, a] B[piv_a, r]
+//   B[piv_b, r]    = Lb^-1 B[piv_b, r]
+//   B[cand_b, r]  -= B[cand_b, a b] B[piv_ab, r]    trailing update, K = 128
 // over the candidate rows only (their ascending list comes from the panel
 // kernel), so the trailing work shrinks as the factorisation proceeds.
 // Solves, left-looking by 128-row blocks, so each block of the result is
@@ -31,7 +34,7 @@ void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int
     f.ctl.skip = skip;
     launch_fill(f, batch, st);
   }
-  for (int k0 = 0; k0 < Mp; k0 += LU_NB) {
+  auto panel = [&](int k0) {
     LuPanelArgs pa;
     pa.T = mat(T, bs, Mp);
     pa.Mp = Mp;
@@ -49,24 +52,44 @@ void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int
     pa.sing_code = code;
     pa.ctl.skip = skip;
     launch_lu_panel(pa, batch, st);
-    const int rest = Mp - k0 - LU_NB;
-    if (rest <= 0) continue;
-    // U12 = L11^-1 B[piv, rest], in place (one row tile: each workgroup owns its columns)
-    GemmArgs u = gemm_args(LU_NB, rest, LU_NB, batch, skip);
+  };
+  // B[piv(k0), c0 : c0 + ncols] = L11(k0)^-1 B[piv(k0), ...], in place (one row tile)
+  auto u12 = [&](int k0, int c0, int ncols) {
+    GemmArgs u = gemm_args(LU_NB, ncols, LU_NB, batch, skip);
     u.A = mat(g.linv + (int64_t)(k0 / LU_NB) * 64 * 64, inv_bs, 64);
-    u.B = mat(T + k0 + LU_NB, bs, Mp, g.perm + k0, Mp);
+    u.B = mat(T + c0, bs, Mp, g.perm + k0, Mp);
     u.C = u.B;
     launch_gemm(u, prec, tile, st, 0);
-    // B[cand, rest] -= B[cand, K] U12
-    GemmArgs t = gemm_args(rest, rest, LU_NB, batch, skip);
-    t.A = mat(T + k0, bs, Mp, g.cand, Mp);
-    t.B = mat(T + k0 + LU_NB, bs, Mp, g.perm + k0, Mp);
+  };
+  // B[rows, c0 : c0 + ncols] -= B[rows, k0 : k0 + K] B[piv(k0 .. k0 + K), c0 : ...]
+  auto update = [&](const int32_t* rows, int nrows, int k0, int K, int c0, int ncols) {
+    GemmArgs t = gemm_args(nrows, ncols, K, batch, skip);
+    t.A = mat(T + k0, bs, Mp, rows, Mp);
+    t.B = mat(T + c0, bs, Mp, g.perm + k0, Mp);
     t.c_kind = SRC_MAT;
-    t.Cin = mat(T + k0 + LU_NB, bs, Mp, g.cand, Mp);
+    t.Cin = mat(T + c0, bs, Mp, rows, Mp);
     t.C = t.Cin;
     t.alpha = -1.0;
     launch_gemm(t, prec, tile, st, 0);
+  };
+  // Panels in pairs (k0, k0 + 64): the second panel's columns are updated by the first
+  // alone, then the columns right of the pair by both at once (inner dimension 128),
+  // which halves the trailing updates and their C traffic.
+  int k0 = 0;
+  for (; k0 + 2 * LU_NB <= Mp; k0 += 2 * LU_NB) {
+    const int kb = k0 + LU_NB, c0 = k0 + 2 * LU_NB;
+    const int rest = Mp - c0;
+    panel(k0);
+    u12(k0, kb, LU_NB);
+    update(g.cand, Mp - kb, k0, LU_NB, kb, LU_NB);  // candidates of the first panel
+    panel(kb);
+    if (rest <= 0) continue;
+    u12(k0, c0, rest);
+    update(g.perm + kb, LU_NB, k0, LU_NB, c0, rest);  // the second panel's pivot rows
+    u12(kb, c0, rest);
+    update(g.cand, rest, k0, 2 * LU_NB, c0, rest);    // candidates of the second panel
   }
+  if (k0 < Mp) panel(k0);  // an odd panel count ends on a single panel
 }
 
 // Y_rows = Y_rows - A_rows Y_src  (rows x nrhs, inner dimension K)
