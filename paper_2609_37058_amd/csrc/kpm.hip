@@ -8,8 +8,8 @@
 // One Chebyshev step on the GPU, with V [N][Mp][Rp] (layer-major, the R
 // columns padded to Rp):
 //   W = c (H - b S) V / a        three batched products over the layers (the
-//                                diagonal, upper and lower blocks of H - b S,
-//                                formed on the fly, one block per batch entry)
+//                                diagonal, upper and lower blocks of b S - H,
+//                                written once per call, one block per batch entry)
 //   W <- S^-1 W                  block-Thomas solve with the factors of S:
 //                                forward  Z_i = W_i - Lf_i Z_{i-1},
 //                                then     X = Dinv Z (one batched product),

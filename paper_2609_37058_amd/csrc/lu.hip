@@ -27,12 +27,11 @@
 // The diagonal blocks L11 and U11 are then inverted by substitution with 8
 // lanes per column (one 8-lane DPP sum per row), and perm, the flags and the
 // ascending list of rows still candidates are written.  The matrix cores then
-// form
-//   B[piv, rest]  = L11^-1 B[piv, rest]          (U12, in place)
-//   B[cand, rest] -= B[cand, K] B[piv, rest]     (l_r U12)
-// Only the multipliers of candidate rows and the U12 rows outside the panel
-// are read back from B; the diagonal 64 x 64 block is represented by the two
-// inverses.
+// form U12 = L11^-1 B[piv, rest] in place and the candidates' trailing update
+// (for pairs of panels, one update with both panels' multipliers; the driver
+// in lu_solve.hip).  Only the multipliers of candidate rows and the U12 rows
+// outside the panel are read back from B; the diagonal 64 x 64 block is
+// represented by the two inverses.
 #include "common.h"
 #include "kernels.h"
 
