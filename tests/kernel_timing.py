@@ -19,6 +19,9 @@ SHAPES = [  # (tile, rows, cols, K, batch, in place, label)
     (128, 960, 960, 64, 64, 0, "LU trailing update at k0 = 0: 960 x 960, K = 64"),
     (128, 896, 896, 128, 64, 0, "the same shape class with K = 128 (896 x 896)"),
     (128, 64, 1024, 64, 64, 1, "U12 / solve diagonal block: 64 x 1024, K = 64, in place"),
+    (64, 64, 1024, 64, 64, 1, "the same with 64 x 64 tiles"),
+    (128, 64, 1024, 128, 64, 0, "64-row product with K = 128: 64 x 1024"),
+    (64, 64, 1024, 128, 64, 0, "the same with 64 x 64 tiles"),
     (128, 128, 1024, 512, 64, 0, "solve update: 128 x 1024, K = 512"),
     (128, 128, 1024, 896, 64, 0, "solve update: 128 x 1024, K = 896"),
     (128, 1024, 1024, 1024, 64, 0, "sweep product: 1024 x 1024, K = 1024"),
@@ -48,7 +51,7 @@ def main():
             print(f"| Mp={Mp} x {nb} | {'FP64' if prec == 0 else 'FP32'} | {names[v]} | {ms.value:.3f} ms | "
                   f"{fl / ms.value / 1e9:.1f} TFLOP/s | rc={rc}", flush=True)
         return
-    shapes = SHAPES[5:6] if "--only-product" in sys.argv else SHAPES
+    shapes = SHAPES[8:9] if "--only-product" in sys.argv else SHAPES
     prec = 1 if "--fp32" in sys.argv else 0
     for tile, rows, cols, K, batch, inplace, label in shapes:
         rc = lib.rgf_ktest_gemm_time(prec, tile, rows, cols, K, batch, inplace, 5, C.byref(ms))
