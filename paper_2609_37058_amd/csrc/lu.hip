@@ -186,14 +186,37 @@ __global__ __launch_bounds__(512) void lu_panel_kernel(LuPanelArgs a) {
         const z64* row = Tb + (int64_t)(tid + i * nt) * ld + k0;
 #pragma clang loop unroll(full)
         for (int t = 0; t < SW; ++t) v[i * SW + (t)] = row[cb + t];
-        for (int m0 = 0; m0 < cb; m0 += 8) {
-          z64 l[8];
+        if constexpr (RPT == 1) {
+          // one row per thread leaves registers to fetch the next 8 multipliers
+          // while the current 8 are applied
+          z64 ln[8];
+          if (cb > 0) {
 #pragma clang loop unroll(full)
-          for (int m = 0; m < 8; ++m) l[m] = row[m0 + m];
+            for (int m = 0; m < 8; ++m) ln[m] = row[m];
+          }
+          for (int m0 = 0; m0 < cb; m0 += 8) {
+            z64 l[8];
 #pragma clang loop unroll(full)
-          for (int m = 0; m < 8; ++m)
+            for (int m = 0; m < 8; ++m) l[m] = ln[m];
+            if (m0 + 8 < cb) {
 #pragma clang loop unroll(full)
-            for (int t = 0; t < SW; ++t) v[i * SW + (t)] = zfms(l[m], U[(m0 + m) * NB + cb + t], v[i * SW + (t)]);
+              for (int m = 0; m < 8; ++m) ln[m] = row[m0 + 8 + m];
+            }
+#pragma clang loop unroll(full)
+            for (int m = 0; m < 8; ++m)
+#pragma clang loop unroll(full)
+              for (int t = 0; t < SW; ++t) v[t] = zfms(l[m], U[(m0 + m) * NB + cb + t], v[t]);
+          }
+        } else {
+          for (int m0 = 0; m0 < cb; m0 += 8) {
+            z64 l[8];
+#pragma clang loop unroll(full)
+            for (int m = 0; m < 8; ++m) l[m] = row[m0 + m];
+#pragma clang loop unroll(full)
+            for (int m = 0; m < 8; ++m)
+#pragma clang loop unroll(full)
+              for (int t = 0; t < SW; ++t) v[i * SW + (t)] = zfms(l[m], U[(m0 + m) * NB + cb + t], v[i * SW + (t)]);
+          }
         }
       }
     }

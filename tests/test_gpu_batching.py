@@ -138,3 +138,26 @@ def test_graph_replays_equal_eager_results(lib, N, M, nE):
         assert fp64_close(eager[0], ref)[0]
     finally:
         lib.set_graphs(False)
+
+
+def test_profile_samples_every_nth_launch(lib):
+    """rgf_profile(n) times one block-product launch in n: the recorded count is the ceiling of
+    the full count over n, and the results do not change while profiling."""
+    dev = synth.random_small_device(7, 130, seed=41)
+    E = np.linspace(-1.5, 1.5, 6)
+    dt = stage(dev)
+    T0, _ = _single(lib, dt, E, 1e-6)
+    counts = {}
+    for every in (1, 3, 4):
+        lib.profile(True, every)
+        lib.profile_read()
+        T, _ = _single(lib, dt, E, 1e-6)
+        n, ms, flops = lib.profile_read()
+        lib.profile(False)
+        counts[every] = n
+        log(f"[profile] every {every}: {n} launches, {ms:.3f} ms, {flops:.3e} flops")
+        assert np.array_equal(T, T0)
+        assert n == 0 or (ms > 0 and flops > 0)
+    assert counts[1] > 0
+    for every in (3, 4):
+        assert counts[every] == -(-counts[1] // every)
