@@ -267,15 +267,8 @@ void Engine::ldos_pass(const rgf_device& d, z64* store, const double* twos, z64*
   // an overlap block as a padded Mp x Mp operand shared by every energy (slot 0..2 of sblk)
   auto shared_s = [&](int slot, const rgf_z* s, bool conj) {
     z64* dst = sblk + (int64_t)slot * MM_;
-    const FormRef f = Sform(s, conj);
-    if (conj) {
-      launch_form_ct(f, mat(dst, MM_, Mp), Mp, 1, st_);
-    } else {
-      FillArgs a = fill_args(mat(dst, MM_, Mp), Mp, Mp, FILL_FORM);
-      a.f = f;
-      launch_fill(a, 1, st_);
-    }
-    return mat(dst, 0, Mp);
+    store_form(Sform(s, conj), dst, 1);
+    return mat(dst, 0, Mp);  // batch stride 0: every energy reads the one block
   };
   auto injected = [&](int q) {  // rho^s of pass layer q, from G_{q-1,0}, G_{q,0}, G_{q+1,0}
     GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
