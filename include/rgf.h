@@ -294,6 +294,26 @@ int transport_stats(void* server, rgf_server_stats* stats);
 const char* rgf_last_error(void);
 const char* rgf_version(void);
 
+/*
+ * Input checks (debug).  The operator z S - H assumes the Hamiltonian and overlap
+ * matrices of a local-orbital basis (paper: Method -- the DFT Hamiltonian and overlap
+ * matrices), Hermitian with S positive definite; the library does not check this by
+ * itself.  rgf_check_device checks on the device, synchronously on `stream`, that every
+ * H_ii, S_ii and both electrodes' H00, S00 are Hermitian to
+ * max |X - X^+| <= tol max(1, max |X|) (|x| = |Re x| + |Im x|), that the diagonal of every
+ * overlap block is real to the same tolerance and positive, and that the entries are
+ * finite; the coupling blocks have no such constraint, and positive diagonals are
+ * necessary for S > 0, not sufficient.  Returns RGF_OK with *max_dev (may be NULL) = the
+ * largest relative deviation, or RGF_EINVAL with rgf_last_error naming the first failing
+ * block.  rgf_set_checks(1) runs the same check with tol = 1e-10 at the start of every
+ * rgf_transmission, rgf_transmission_bias, rgf_transmission_batch, rgf_ldos and (device
+ * blocks only) rgf_kpm_moments call, which then fails with its error; it synchronizes the
+ * stream, so it is off by default.
+ */
+int rgf_check_device(const rgf_device* dev, double tol, double* max_dev, void* stream);
+int rgf_set_checks(int enable);
+int rgf_get_checks(void);
+
 /* Release every cached device workspace of the current device (sweep workspaces, batch job
    buffers, k-mesh and KPM arenas); synchronizes the device first. */
 int rgf_release_workspaces(void);

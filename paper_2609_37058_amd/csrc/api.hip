@@ -212,6 +212,58 @@ void check_device(const rgf_device& d) {
   check_lead(d.right, d.M, "right lead");
 }
 
+// ------------------------------------------------------------ input checks
+static int g_checks = 0;
+bool input_checks() { return g_checks != 0; }
+
+// Hermiticity of every H_ii, S_ii (and of the electrodes' H00, S00 when `leads`), and a
+// positive real diagonal of every overlap block.  Synchronous; throws RGF_EINVAL naming
+// the first block that fails.  Returns max |X - X^+| / max(1, max |X|) over the blocks.
+double check_inputs(const rgf_device& d, double tol, bool leads, hipStream_t st) {
+  struct Arr {
+    const rgf_z* p;
+    int nblk;
+    bool overlap;
+    const char* name;
+  };
+  std::vector<Arr> arrs = {{d.Hd, d.N, false, "H_ii"}, {d.Sd, d.N, true, "S_ii"}};
+  if (leads) {
+    arrs.push_back({d.left.H00, 1, false, "left electrode H00"});
+    arrs.push_back({d.left.S00, 1, true, "left electrode S00"});
+    arrs.push_back({d.right.H00, 1, false, "right electrode H00"});
+    arrs.push_back({d.right.S00, 1, true, "right electrode S00"});
+  }
+  int total = 0;
+  for (const Arr& a : arrs) total += a.nblk;
+  double* dev_out = nullptr;
+  RGF_HIP(hipMalloc((void**)&dev_out, sizeof(double) * 4 * total));
+  std::vector<double> out(4 * (size_t)total);
+  int off = 0;
+  for (const Arr& a : arrs) {
+    launch_herm_check(reinterpret_cast<const z64*>(a.p), d.M, a.nblk, dev_out + 4 * off, st);
+    off += a.nblk;
+  }
+  RGF_HIP(hipMemcpyAsync(out.data(), dev_out, sizeof(double) * 4 * total, hipMemcpyDeviceToHost, st));
+  RGF_HIP(hipStreamSynchronize(st));
+  RGF_HIP(hipFree(dev_out));
+  double worst = 0.0;
+  off = 0;
+  for (const Arr& a : arrs) {
+    for (int b = 0; b < a.nblk; ++b, ++off) {
+      const double* o = out.data() + 4 * off;
+      const double scale = std::max(1.0, o[1]), dev = o[0] / scale;
+      worst = std::max(worst, dev);
+      const std::string where = std::string(a.name) + (a.nblk > 1 ? " of layer " + std::to_string(b) : "");
+      RGF_CHECK(std::isfinite(o[0]) && std::isfinite(o[1]), RGF_EINVAL, "non-finite entries in " + where);
+      RGF_CHECK(dev <= tol, RGF_EINVAL, "not Hermitian: " + where + " (max |X - X^+| / max(1, max |X|) = " +
+                                            std::to_string(dev) + ")");
+      RGF_CHECK(!a.overlap || (o[2] > 0.0 && o[3] <= tol * scale), RGF_EINVAL,
+                "overlap diagonal not real and positive: " + where);
+    }
+  }
+  return worst;
+}
+
 bool uses_small_path(int M, int precision) {
   int small_max = SMALL_MAX_M;
   if (const char* s = std::getenv("RGF_SMALL_MAX_M")) small_max = std::min(SMALL_MAX_M, std::atoi(s));
@@ -715,6 +767,7 @@ int rgf_transmission(const rgf_device* dev, const double* E, int64_t nE, double 
     RGF_CHECK(dev, RGF_EINVAL, "null device");
     check_device(*dev);
     check_common(E, nE, eta, precision, T);
+    if (g_checks) check_inputs(*dev, INPUT_CHECK_TOL, true, (hipStream_t)stream);
     if (nE == 0) return;
     transmission_impl(*dev, E, nE, eta, precision, T, info, (hipStream_t)stream);
   });
@@ -727,6 +780,7 @@ int rgf_transmission_bias(const rgf_device* dev, const double* E, int64_t nE, do
     check_device(*dev);
     check_common(E, nE, eta, precision, T);
     RGF_CHECK(std::isfinite(u_left) && std::isfinite(u_right), RGF_EINVAL, "electrode shifts must be finite");
+    if (g_checks) check_inputs(*dev, INPUT_CHECK_TOL, true, (hipStream_t)stream);
     if (nE == 0) return;
     transmission_impl(*dev, E, nE, eta, precision, T, info, (hipStream_t)stream, u_left, u_right);
   });
@@ -739,6 +793,7 @@ int rgf_ldos(const rgf_device* dev, const double* E, int64_t nE, double eta, dou
     check_device(*dev);
     RGF_CHECK(dos || ados_left || ados_right, RGF_EINVAL, "no output requested");
     check_common(E, nE, eta, RGF_FP64, dos ? dos : (ados_left ? ados_left : ados_right));
+    if (g_checks) check_inputs(*dev, INPUT_CHECK_TOL, true, (hipStream_t)stream);
     if (nE == 0) return;
     ldos_impl(*dev, E, nE, eta, dos, ados_left, ados_right, info, (hipStream_t)stream);
   });
@@ -764,6 +819,7 @@ int rgf_transmission_batch(const rgf_device* devs, int32_t ndev, const double* c
     for (int d = 0; d < ndev; ++d) {
       check_device(devs[d]);
       check_common(E[d], nE[d], eta, precision, T[d]);
+      if (g_checks) check_inputs(devs[d], INPUT_CHECK_TOL, true, (hipStream_t)stream);
     }
     transmission_batch_impl(devs, ndev, E, nE, eta, precision, T, info, (hipStream_t)stream);
   });
@@ -872,6 +928,22 @@ int rgf_set_graphs(int enable) {
 }
 
 int rgf_get_graphs(void) { return graphs_enabled() ? 1 : 0; }
+
+int rgf_set_checks(int enable) {
+  return guarded([&] { g_checks = enable ? 1 : 0; });
+}
+
+int rgf_get_checks(void) { return g_checks; }
+
+int rgf_check_device(const rgf_device* dev, double tol, double* max_dev, void* stream) {
+  return guarded([&] {
+    RGF_CHECK(dev, RGF_EINVAL, "null device");
+    check_device(*dev);
+    RGF_CHECK(std::isfinite(tol) && tol >= 0.0, RGF_EINVAL, "tol must be finite and >= 0");
+    const double w = check_inputs(*dev, tol, true, (hipStream_t)stream);
+    if (max_dev) *max_dev = w;
+  });
+}
 
 int rgf_get_tuning(int32_t M, int precision, int32_t* tile, int32_t* lanes) {
   return guarded([&] {

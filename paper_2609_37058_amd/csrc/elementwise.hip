@@ -75,6 +75,40 @@ __global__ __launch_bounds__(ET) void form_ct_kernel(FormRef f, MatRef dst, int 
   }
 }
 
+// Input check of `nblk` consecutive M x M blocks (block b at X + b M^2): out[4 b ..] =
+// max |X - X^+| (component-wise sum), max |X| (the same measure), min Re X_ii, max |Im X_ii|.
+// One workgroup per block; max and min do not depend on the reduction order.
+__global__ __launch_bounds__(ET) void herm_check_kernel(const z64* X, int M, double* out) {
+  __shared__ double red[4][ET];
+  const z64* B = X + (int64_t)blockIdx.x * M * M;
+  double asym = 0.0, amax = 0.0, dmin = 1.0e300, dim = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)M * M; e += ET) {
+    const int r = (int)(e / M), c = (int)(e % M);
+    const z64 x = B[e], y = B[(int64_t)c * M + r];
+    asym = fmax(asym, fabs(x.x - y.x) + fabs(x.y + y.y));
+    amax = fmax(amax, fabs(x.x) + fabs(x.y));
+    if (r == c) {
+      dmin = fmin(dmin, x.x);
+      dim = fmax(dim, fabs(x.y));
+    }
+  }
+  red[0][threadIdx.x] = asym;
+  red[1][threadIdx.x] = amax;
+  red[2][threadIdx.x] = dmin;
+  red[3][threadIdx.x] = dim;
+  __syncthreads();
+  for (int w = ET / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+      red[2][threadIdx.x] = fmin(red[2][threadIdx.x], red[2][threadIdx.x + w]);
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[4 * (int64_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
 __global__ __launch_bounds__(ET) void axpy_kernel(MatRef dst, MatRef src, double s, int rows, int cols,
                                                    BatchCtl ctl) {
   const int b = blockIdx.y;
@@ -342,6 +376,12 @@ void launch_fill(const FillArgs& a, int batch, hipStream_t st) {
   if (batch <= 0) return;
   const int64_t n = std::max<int64_t>((int64_t)a.rows * a.cols, a.flags ? a.flags_n : 0);
   hipLaunchKernelGGL(fill_kernel, dim3(nblocks(n), batch), dim3(ET), 0, st, a);
+  RGF_HIP(hipGetLastError());
+}
+
+void launch_herm_check(const z64* X, int M, int nblk, double* out, hipStream_t st) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(herm_check_kernel, dim3((unsigned)nblk), dim3(ET), 0, st, X, M, out);
   RGF_HIP(hipGetLastError());
 }
 

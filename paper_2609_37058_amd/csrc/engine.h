@@ -125,6 +125,12 @@ struct Grouping {
 
 // ---- one device through the path (api.hip) ----
 void check_device(const rgf_device& d);
+// Debug input checks (rgf_set_checks): Hermitian H_ii, S_ii (and the electrodes' H00, S00 when
+// `leads`), overlap diagonals real and positive; synchronous, throws RGF_EINVAL naming the first
+// failing block, returns max |X - X^+| / max(1, max |X|).
+constexpr double INPUT_CHECK_TOL = 1e-10;
+bool input_checks();
+double check_inputs(const rgf_device& d, double tol, bool leads, hipStream_t st);
 bool uses_small_path(int M, int precision);
 SmallArgs small_args(const rgf_device& d, const double* E, int64_t nE, double eta, double* T, int32_t* info);
 // the whole path for one device on one stream (no lanes); mem_share scales the

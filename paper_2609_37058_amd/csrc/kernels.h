@@ -139,6 +139,9 @@ void launch_fill(const FillArgs& a, int batch, hipStream_t st);
 // dst[b] (Mp x Mp) = the formed operand f with f.conj_t taken as set: z_b S^+ - H^+,
 // padded like a formed operand; f.sub must be unset.
 void launch_form_ct(const FormRef& f, MatRef dst, int Mp, int batch, hipStream_t st);
+// out[4 b .. 4 b + 3] for each of nblk consecutive M x M blocks of X: max |X - X^+|, max |X|
+// (component-wise |re| + |im| measures), min Re of the diagonal, max |Im| of the diagonal
+void launch_herm_check(const z64* X, int M, int nblk, double* out, hipStream_t st);
 // A fill of `kind` into dst (rows x cols) with no source, no row gather and scale 1.
 inline FillArgs fill_args(MatRef dst, int rows, int cols, int kind) {
   FillArgs f;

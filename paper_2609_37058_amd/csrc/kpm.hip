@@ -429,6 +429,7 @@ int rgf_kpm_moments(const rgf_device* dev, double e_min, double e_max, int32_t n
     RGF_CHECK(n_mom >= 1 && R >= 1, RGF_EINVAL, "n_mom and R must be >= 1");
     RGF_CHECK(std::isfinite(e_min) && std::isfinite(e_max) && e_max > e_min, RGF_EINVAL,
               "spectral bounds must be finite with e_max > e_min");
+    if (input_checks()) check_inputs(*dev, INPUT_CHECK_TOL, false, (hipStream_t)stream);  // no electrodes here
     kpm_moments_impl(*dev, e_min, e_max, n_mom, vectors, R, mu, (hipStream_t)stream);
     return RGF_OK;
   } catch (const Error& e) {

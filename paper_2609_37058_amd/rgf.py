@@ -67,6 +67,9 @@ SIGNATURES = {
     "rgf_version": (C.c_char_p, []),
     "rgf_release_workspaces": (C.c_int, []),
     "rgf_profile": (C.c_int, [C.c_int]),
+    "rgf_check_device": (C.c_int, [C.POINTER(rgf_device), C.c_double, C.POINTER(C.c_double), C.c_void_p]),
+    "rgf_set_checks": (C.c_int, [C.c_int]),
+    "rgf_get_checks": (C.c_int, []),
     "rgf_profile_read": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rgf_get_tile": (C.c_int, [C.c_int, C.POINTER(C.c_int32)]),
     "rgf_set_mixed_parts": (C.c_int, [C.c_int]),
@@ -353,6 +356,24 @@ def lead_self_energy(lead: LeadTensors, side: int, E: torch.Tensor, eta: float, 
 
 def release_workspaces():
     _check(load().rgf_release_workspaces())
+
+
+def check_device(dev: DeviceTensors, tol: float = 1e-10, stream=None) -> float:
+    """Hermiticity and overlap-diagonal check of the device and electrode blocks (raises RgfError
+    naming the first failing block); returns the largest relative deviation."""
+    w = C.c_double()
+    d = dev.cstruct()
+    _check(load().rgf_check_device(C.byref(d), float(tol), C.byref(w), _stream(stream)))
+    return w.value
+
+
+def set_checks(enable: bool):
+    """Run check_device at the start of every transmission, LDOS and KPM call (synchronizes)."""
+    _check(load().rgf_set_checks(1 if enable else 0))
+
+
+def get_checks() -> bool:
+    return bool(load().rgf_get_checks())
 
 
 def profile(enable: bool, every: int = 1):

@@ -61,6 +61,10 @@ def test_argument_errors_before_device_work(lib):
     assert L.rgf_kpm_fermi(None, 10, 1.0, -1.0, 3.0, None, None) == rgf.RGF_EINVAL
     assert L.rgf_kpm_dos(None, 0, -1.0, 1.0, None, 5, None, None) == rgf.RGF_EINVAL
     assert L.rgf_profile(-1) == rgf.RGF_EINVAL
+    assert L.rgf_check_device(None, 1e-10, None, None) == rgf.RGF_EINVAL
+    assert L.rgf_check_device(C.byref(d), 1e-10, None, None) == rgf.RGF_EINVAL  # null blocks, no device work
+    assert L.rgf_set_checks(1) == rgf.RGF_OK and L.rgf_get_checks() == 1
+    assert L.rgf_set_checks(0) == rgf.RGF_OK and L.rgf_get_checks() == 0
     assert L.rgf_profile(16) == rgf.RGF_OK and L.rgf_profile(0) == rgf.RGF_OK
 
 

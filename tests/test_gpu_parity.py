@@ -84,3 +84,36 @@ def test_blocks_above_1024(lib):
     ok, rel, ab = fp64_close(T, ref)
     log(f"[parity] M=1100: max rel {rel:.2e} max abs {ab:.2e}")
     assert ok and np.all(info == 0)
+
+
+def test_input_checks(lib):
+    """rgf_check_device accepts the Hermitian test devices and names the first block that is
+    not Hermitian or whose overlap diagonal is not positive; with rgf_set_checks(1) the
+    transmission call fails the same way, and without it runs."""
+    import torch
+    dev = synth.random_small_device(4, 70, seed=12, distinct_leads=True)
+    E = torch.linspace(-1.0, 1.0, 3, dtype=torch.float64, device="cuda")
+    dt = stage(dev)
+    assert lib.check_device(dt) <= 1e-14
+    bad = stage(dev)
+    bad.Hd[2, 5, 9] += 0.3  # breaks H_22 = H_22^+
+    with pytest.raises(lib.RgfError, match="H_ii of layer 2"):
+        lib.check_device(bad)
+    neg = stage(dev)
+    neg.Sd[1].mul_(-1.0)  # Hermitian, but not positive
+    with pytest.raises(lib.RgfError, match="overlap diagonal"):
+        lib.check_device(neg)
+    T0, _ = lib.transmission(bad, E, 1e-6)  # unchecked calls run on any input
+    torch.cuda.synchronize()
+    lib.set_checks(True)
+    try:
+        with pytest.raises(lib.RgfError, match="not Hermitian"):
+            lib.transmission(bad, E, 1e-6)
+        T, _ = lib.transmission(dt, E, 1e-6)
+        torch.cuda.synchronize()
+        assert torch.isfinite(T).all()
+        r = torch.ones((dev.N * dev.M, 2), dtype=torch.complex128, device="cuda")
+        with pytest.raises(lib.RgfError, match="overlap diagonal"):
+            lib.kpm_moments(neg, -10.0, 10.0, 4, r)
+    finally:
+        lib.set_checks(False)
