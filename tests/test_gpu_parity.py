@@ -117,3 +117,33 @@ def test_input_checks(lib):
             lib.kpm_moments(neg, -10.0, 10.0, 4, r)
     finally:
         lib.set_checks(False)
+
+
+@pytest.mark.parametrize("M", [8, 40])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_zero_coupling_block_gives_zero(lib, M, precision):
+    """A device cut in two by a zero coupling block (H_{2,3} = S_{2,3} = 0) transmits nothing:
+    T = 0 exactly on every energy (the oracle's pin of the same case), with no info bit set."""
+    import torch
+    from paper_2609_37058_amd import staging
+    dev = synth.random_small_device(5, M, seed=300 + M, distinct_leads=True)
+    hd, hu, sd, su = dev.stacked()
+    hu[2] = 0.0
+    su[2] = 0.0
+    L, R = dev.left, dev.right
+    dt = staging.stage_blocks(hd, hu, sd, su, staging.stage_lead(L.H00, L.H01, L.S00, L.S01),
+                              staging.stage_lead(R.H00, R.H01, R.S00, R.S01))
+    E = torch.as_tensor(np.array([-1.7, -0.4, 0.3, 1.2])).cuda()
+    T, info = lib.transmission(dt, E, 1e-6, precision)
+    torch.cuda.synchronize()
+    log(f"[parity] zero coupling M={M} {precision}: T={T.cpu().numpy()}")
+    assert torch.all(T == 0.0) and torch.all(info == 0)
+
+
+def test_empty_energy_grid(lib):
+    """nE = 0 is legal: nothing is launched and the outputs are empty."""
+    import torch
+    dt = stage(synth.random_small_device(3, 20, seed=5))
+    T, info = lib.transmission(dt, torch.empty(0, dtype=torch.float64, device="cuda"), 1e-6)
+    torch.cuda.synchronize()
+    assert T.numel() == 0 and info.numel() == 0
