@@ -225,7 +225,9 @@ void kpm_moments_impl(const rgf_device& d, double e_min, double e_max, int n_mom
   const int64_t VB = (int64_t)Mp * Rp;  // one layer of a vector panel
   const int64_t VN = (int64_t)N * VB;
   const double a = (e_max - e_min) / (2.0 - KPM_EPS), b = 0.5 * (e_max + e_min);
-  const int tile = tile_for(PREC_F64, Mp);
+  // the factorisation of S runs one block at a time: 64 x 64 tiles give its products
+  // four times the workgroups of the batched default
+  const int tile = KPM_TILE;
 
   // ---- memory: factors, vector panels, lu buffers, constants ----
   size_t off = 0;
