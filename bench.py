@@ -11,14 +11,23 @@ resident in HBM before the timed region; staging is not timed.
 
 Prints one JSON line (see the keys below).  The FP64 path is the headline
 ``value``; the mixed path is measured beside it with --precision both.
+
+Wall budget: a C4 step takes about half a minute, so --steps/--warmup are
+upper bounds.  After the first warm-up step the timed step counts of each
+precision are cut to what fits --budget-s (counted from process start,
+interpreter start-up included) next to the CPU baseline and a safety
+margin; the line reports the counts actually run beside the requested ones.
 """
 from __future__ import annotations
 
-import argparse
-import json
-import os
-import sys
 import time
+
+START = time.perf_counter()  # the wall budget counts from here
+
+import argparse  # noqa: E402
+import json  # noqa: E402
+import os  # noqa: E402
+import sys  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -32,8 +41,14 @@ METRIC = "RGF energy-point*layers/s at block 1024 (FP64 vs mixed); p50/p99 solve
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1, help="timed steps per precision (an upper bound, see --budget-s)")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed steps per precision (upper bound; at least 1)")
+    ap.add_argument("--budget-s", type=float, default=400.0,
+                    help="wall-clock budget of the whole run in seconds, from process start (c4 workload)")
+    ap.add_argument("--timed-s", type=float, default=100.0,
+                    help="upper bound on the FP64 timed region in seconds (the mixed pass gets half of it)")
+    ap.add_argument("--profile-every", type=int, default=1,
+                    help="c4: time every n-th launch of each kernel class (0: the sweep products only)")
     ap.add_argument("--energies-per-step", type=int, default=128)
     ap.add_argument("--layers", type=int, default=400, help="principal layers (400 = the full workload)")
     ap.add_argument("--block", type=int, default=1024, help="block size M (1024 = the full workload)")
@@ -41,12 +56,19 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="block-product tile (64/128); 0 = library default")
-    ap.add_argument("--workload", choices=["c4", "bias", "kmesh", "ldos", "kpm", "serve"], default="c4",
+    ap.add_argument("--workload", choices=["c4", "bias", "kmesh", "ldos", "kpm", "serve", "kernels"],
+                    default="c4",
                     help="c4: the headline zero-bias workload; bias: the C4 device at finite bias with the "
                          "Landauer current; kmesh: a transversely periodic C2-type device on a 7x7 k-mesh; "
                          "ldos: orbital-resolved LDOS and both injected parts of the C3 device; "
                          "kpm: Chebyshev moments and the Fermi level of the C4 central region; "
-                         "serve: a C5-type request stream through the serving loop (p50/p99 latency)")
+                         "serve: a C5-type request stream through the serving loop (p50/p99 latency); "
+                         "kernels: isolated timings of the C4 layer's block-product shapes and of the batched LU "
+                         "through the test-only harness librgf_ktest.so (prints a table, no JSON line)")
+    ap.add_argument("--only-product", action="store_true", help="kernels: the sweep product shape only")
+    ap.add_argument("--sweep-variants", action="store_true",
+                    help="kernels: the sweep products with each operand form, FP64 and FP32")
+    ap.add_argument("--fp32", action="store_true", help="kernels: FP32 matrix cores (the mixed form)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (read once, written once), three "
                          "times, and exit: the reference kernel that scales the HBM byte counters")
@@ -70,12 +92,15 @@ def copy_probe(mib: int) -> int:
 def cpu_baseline(cfg, budget_s: float):
     """The FP64 oracle, as it stands, timed on the host on a bounded sample of the workload.
 
-    Sample: one energy of the grid (the middle one) through ``oracle.transmission``
-    on the first n layers of the same device (same principal layer, same
-    dopants, same leads): lead decimation, self-energies, block-Thomas
-    elimination and back-substitution, Caroli trace.  n is sized so the run
-    takes about ``budget_s`` seconds; the rate is n / wall time, in the
-    benchmark's unit (energy-point x layers per second, decimation included).
+    Sample: one energy of the grid (the middle one).  Its two parts are timed
+    with the oracle's own functions: the lead decimation and self-energies
+    (``oracle.self_energies``: one decimation, since both electrodes are the
+    same lead) and the device solve (``oracle.transmission_block_thomas``:
+    block-Thomas elimination, back-substitution and the Caroli trace) on the
+    first n layers of the same device, n sized to the budget.  The rate for
+    one energy of the whole N-layer device is N / (t_leads + N t_layer) with
+    t_layer = t_device / n, in the benchmark's unit (energy-point x layers per
+    second, decimation included).
     """
     from threadpoolctl import threadpool_info
     import oracle
@@ -83,23 +108,28 @@ def cpu_baseline(cfg, budget_s: float):
 
     dev = cfg.device
     E = float(cfg.energies[len(cfg.energies) // 2])
-    # about 0.4 s per layer and 10 s of decimation at M = 1024 on 8 cores; scale as M^3
-    scale = (dev.M / 1024.0) ** 3
-    n = int(max(2, min(dev.N, (budget_s - 10.0 * scale) / max(0.4 * scale, 1e-3))))
+    z = complex(E, cfg.eta)
+    t0 = time.perf_counter()
+    sl, sr, info = oracle.self_energies(dev.left, dev.right, z)
+    t_leads = time.perf_counter() - t0
+    # about 0.4 s per layer at M = 1024 on 8 cores; scale as M^3
+    per = 0.4 * (dev.M / 1024.0) ** 3
+    n = int(max(2, min(dev.N, (budget_s - t_leads) / max(per, 1e-3))))
     sub = synth.Device(n, dev.M, dev.left, dev.right, base=dev.base,
                        shifts={k: v for k, v in dev.shifts.items() if k < n}, name=dev.name + f"-first{n}")
     t0 = time.perf_counter()
-    oracle.transmission(sub, [E], cfg.eta, method="thomas")
-    wall = time.perf_counter() - t0
+    oracle.transmission_block_thomas(sub, z, sl, sr)
+    t_dev = time.perf_counter() - t0
+    t_layer = t_dev / n
     threads = max((p.get("num_threads", 1) for p in threadpool_info()), default=1)
     return {
-        "value": n / wall,
+        "value": dev.N / (t_leads + dev.N * t_layer),
         "unit": "energy-point*layers/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"oracle.transmission (numpy/scipy FP64, block-Thomas) on 1 energy (E={E:.4f} eV) "
-                   f"and the first {n} of {dev.N} layers of the workload device, decimation included; "
-                   f"{wall:.1f} s wall"),
+        "sample": (f"1 energy (E={E:.4f} eV): oracle.self_energies (one decimation, {info['iters_left']} steps) "
+                   f"{t_leads:.1f} s, oracle.transmission_block_thomas on the first {n} of {dev.N} layers "
+                   f"{t_dev:.1f} s ({t_layer:.3f} s per layer); rate = {dev.N} / (t_leads + {dev.N} t_layer)"),
     }
 
 
@@ -360,22 +390,108 @@ def run_extra_workload(args) -> int:
     return 0
 
 
+PEAKS = {"fp64": FP64_MFMA_PEAK_TFLOPS, "fp32": FP32_MFMA_PEAK_TFLOPS}
+CLASS_NAMES = {
+    "sweep": "sweep block products W <- -W X, B' = A - L X (zgemm role 1)",
+    "lu_update": "LU trailing updates (zgemm role 0, more than 64 rows)",
+    "solve": "triangular-solve updates (zgemm role 0, more than 64 rows)",
+    "row64": "64-row products: U12 blocks, diagonal-block inverses applied (zgemm role 0)",
+    "panel": "LU panels: pivot search and in-panel elimination (vector units, no matrix-core flops)",
+    "lead": "decimation and self-energy products and panels",
+    "other": "final block inverse, G_1N and trace products",
+}
+
+
+def class_rooflines(cls: dict, prec: str, mixed_parts: int = 7) -> dict:
+    """Per kernel class: share of the summed kernel time, achieved rate on the timed launches and
+    its fraction of the matrix-core peak of the class's own arithmetic type."""
+    total_ms = sum(c["ms"] for c in cls.values())
+    out = {}
+    for name, c in cls.items():
+        if c["timed_launches"] == 0 and c["launches"] == 0:
+            continue
+        fp32 = prec == "mixed" and ((name == "sweep" and mixed_parts & 1) or (name == "lu_update" and mixed_parts & 2)
+                                    or (name == "solve" and mixed_parts & 4)
+                                    or (name == "row64" and mixed_parts & 6))
+        peak = PEAKS["fp32" if fp32 else "fp64"]
+        ach = c["timed_flops"] / (c["ms"] / 1e3) / 1e12 if c["ms"] > 0 and c["timed_flops"] > 0 else None
+        out[name] = {
+            "what": CLASS_NAMES[name],
+            "share_of_kernel_time": c["ms"] / total_ms if total_ms > 0 else None,
+            "timed_launches": c["timed_launches"], "avg_launch_ms": c["ms"] / max(1, c["timed_launches"]),
+            "launches": c["launches"], "flops": c["flops"],
+            "achieved_tflops": ach, "peak_tflops": peak, "frac": (ach / peak) if ach else None,
+        }
+    return out
+
+
+def run_kernel_timing(args) -> int:
+    """Isolated timings of the block-product shapes of one C4 layer (Mp = 1024, 64 energies per
+    launch), the skinny KPM products and the batched LU, through the test-only harness
+    librgf_ktest.so; microseconds and TFLOP/s (8 real flops per complex multiply-add) per shape."""
+    import ctypes as C
+    import torch
+    shapes = [  # (tile, rows, cols, K, batch, in place, label)
+        (128, 960, 960, 64, 64, 0, "LU trailing update at k0 = 0: 960 x 960, K = 64"),
+        (128, 896, 896, 128, 64, 0, "the same shape class with K = 128 (896 x 896)"),
+        (128, 64, 1024, 64, 64, 1, "U12 / solve diagonal block: 64 x 1024, K = 64, in place"),
+        (64, 64, 1024, 64, 64, 1, "the same with 64 x 64 tiles"),
+        (128, 64, 1024, 128, 64, 0, "64-row product with K = 128: 64 x 1024"),
+        (64, 64, 1024, 128, 64, 0, "the same with 64 x 64 tiles"),
+        (128, 128, 1024, 512, 64, 0, "solve update: 128 x 1024, K = 512"),
+        (128, 128, 1024, 896, 64, 0, "solve update: 128 x 1024, K = 896"),
+        (128, 1024, 1024, 1024, 64, 0, "sweep product: 1024 x 1024, K = 1024"),
+        (64, 1024, 64, 1024, 1, 0, "one unsplit KPM sweep step: 1024 x 64, K = 1024, batch 1"),
+        (64, 1024, 64, 64, 16, 0, "the same step as 16 chunks of K = 64 in one launch"),
+        (64, 1024, 64, 1024, 400, 0, "KPM layer-batched product: 1024 x 64, K = 1024, batch 400"),
+    ]
+    lib = C.CDLL(os.path.join(ROOT, "paper_2609_37058_amd", "librgf_ktest.so"))
+    lib.rgf_ktest_gemm_time.argtypes = [C.c_int] * 8 + [C.POINTER(C.c_double)]
+    lib.rgf_ktest_lu_time.argtypes = [C.c_int] * 5 + [C.POINTER(C.c_double)] * 2
+    lib.rgf_ktest_sweep_time.argtypes = [C.c_int] * 5 + [C.POINTER(C.c_double)]
+    torch.cuda.init()
+    ms = C.c_double()
+    if args.sweep_variants:
+        names = ["W' = -W X, stored operands", "B' = A - L X, L adjoint-formed, A formed",
+                 "B' with L stored, A formed", "B' with L formed untransposed", "-L X, L adjoint-formed, no C",
+                 "adjoint formation kernel + B' with L stored"]
+        cases = [(Mp, nb, prec, v) for Mp, nb in ((1024, 64), (512, 64), (256, 128)) for prec in (0, 1)
+                 for v in range(len(names)) if Mp == 1024 or v in (0, 1, 5)]
+        for Mp, nb, prec, v in cases:
+            rc = lib.rgf_ktest_sweep_time(prec, v, Mp, nb, 5, C.byref(ms))
+            fl = 8.0 * Mp ** 3 * nb
+            print(f"| Mp={Mp} x {nb} | {'FP64' if prec == 0 else 'FP32'} | {names[v]} | {ms.value:.3f} ms | "
+                  f"{fl / ms.value / 1e9:.1f} TFLOP/s | rc={rc}", flush=True)
+        return 0
+    prec = 1 if args.fp32 else 0
+    for tile, rows, cols, K, batch, inplace, label in (shapes[8:9] if args.only_product else shapes):
+        rc = lib.rgf_ktest_gemm_time(prec, tile, rows, cols, K, batch, inplace, 5, C.byref(ms))
+        fl = 8.0 * rows * cols * K * batch
+        print(f"| {label} | {ms.value * 1e3:.1f} | {fl / ms.value / 1e9:.1f} | rc={rc}", flush=True)
+    if args.only_product:
+        return 0
+    f, sv = C.c_double(), C.c_double()
+    for Mp in (256, 512, 1024):
+        rc = lib.rgf_ktest_lu_time(prec, Mp, Mp, 64, 3, C.byref(f), C.byref(sv))
+        print(f"LU Mp={Mp}, 64 energies: factor {f.value:.2f} ms, solves {sv.value:.2f} ms rc={rc}", flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.copy_probe_mib:
         return copy_probe(args.copy_probe_mib)
-    if args.workload == "serve":
-        if args.gpus != 1:
-            print("bench.py measures one GPU only", file=sys.stderr)
-            return 2
-        return run_serving(args)
-    if args.workload != "c4":
-        return run_extra_workload(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (one process, one MI355X); --gpus {args.gpus} is not supported. "
               "The path shards over energies with no exchange during compute; see the design notes.",
               file=sys.stderr)
         return 2
+    if args.workload == "kernels":
+        return run_kernel_timing(args)
+    if args.workload == "serve":
+        return run_serving(args)
+    if args.workload != "c4":
+        return run_extra_workload(args)
     import numpy as np
     import torch
     import synth
@@ -396,93 +512,145 @@ def main():
         rgf.set_tile("fp64", args.tile)
         rgf.set_tile("mixed", args.tile)
     torch.cuda.synchronize()
+    deadline = START + args.budget_s
+    left = lambda: deadline - time.perf_counter()
+    # what must still fit after the FP64 pass: the decimation timing, the CPU baseline, a margin
+    tail_s = 15.0 + (0.0 if args.no_cpu_baseline else args.cpu_seconds + 10.0)
 
     stream = torch.cuda.current_stream()
     precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     results = {}
-    for prec in precisions:
-        def step(k):
-            lo = (k * B) % nE
+    T_by_step = {}
+    every = max(0, args.profile_every)
+    for pi, prec in enumerate(precisions):
+        def step(j):
+            lo = (j * B) % nE
             Eb = E_all[lo:lo + B]
             if Eb.numel() < B:
                 Eb = torch.cat([Eb, E_all[:B - Eb.numel()]])
             return rgf.transmission(dev_t, Eb, cfg.eta, prec)
 
-        for k in range(args.warmup):
-            print(f"[bench] {prec} warmup step {k}", file=sys.stderr, flush=True)
-            T, info = step(k)
+        # warm-up: the first step always (workspaces, first launches); more while they fit
+        n_warm = 0
+        t0 = time.perf_counter()
+        print(f"[bench] {prec} warmup step 0", file=sys.stderr, flush=True)
+        step(0)
         torch.cuda.synchronize()
-        rgf.profile(True)
-        rgf.profile_read()
-        lat = []
-        infos = []
+        step_s = time.perf_counter() - t0
+        n_warm = 1
+        # the mixed pass still to come: its warm-up and its timed region (about 0.7 x this step)
+        later = sum(0.7 * step_s + 0.5 * args.timed_s for q in precisions[pi + 1:])
+        timed_cap = args.timed_s if prec == "fp64" else 0.5 * args.timed_s
+        # timed steps first; further warm-up steps only where the budget leaves room for them
+        fit = int(min(left() - tail_s - later, timed_cap) // step_s)
+        n_steps = max(1, min(args.steps, fit))
+        spare = left() - tail_s - later - n_steps * step_s
+        while n_warm < args.warmup and spare > step_s:
+            print(f"[bench] {prec} warmup step {n_warm}", file=sys.stderr, flush=True)
+            step(n_warm)
+            torch.cuda.synchronize()
+            n_warm += 1
+            spare -= step_s
+        print(f"[bench] {prec}: one step {step_s:.1f} s; {n_steps} timed of {args.steps} requested "
+              f"({left():.0f} s of the budget left)", file=sys.stderr, flush=True)
+        if every > 0:
+            rgf.profile_classes(True, every)
+        else:
+            rgf.profile(True)
+        rgf.profile_read_classes()
+        lat, infos = [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(args.steps):
+        for j in range(n_steps):
             ev0 = torch.cuda.Event(enable_timing=True)
             ev1 = torch.cuda.Event(enable_timing=True)
             ev0.record(stream)
-            T, info = step(args.warmup + k)
+            T, info = step(j)
             ev1.record(stream)
             infos.append(info)
             ev1.synchronize()
             lat.append(ev0.elapsed_time(ev1) / 1e3)
-            print(f"[bench] {prec} step {k}: {lat[-1]:.2f} s", file=sys.stderr, flush=True)
+            T_by_step.setdefault(prec, {})[j] = T.cpu().numpy()
+            print(f"[bench] {prec} step {j}: {lat[-1]:.2f} s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        n_launch, k_ms, k_flops = rgf.profile_read()
+        wall = time.perf_counter() - t0
+        cls = rgf.profile_read_classes()
         rgf.profile(False)
         bad = int(sum(int((i != 0).sum().item()) for i in infos))
-        wall = t1 - t0
         results[prec] = {
-            "value": args.steps * B * d.N / wall,
-            "ms_per_step": wall / args.steps * 1e3,
+            "value": n_steps * B * d.N / wall,
+            "ms_per_step": wall / n_steps * 1e3,
+            "steps": n_steps, "warmup": n_warm,
             "lat": lat,
-            "kernel": {"launches": n_launch, "ms": k_ms, "flops": k_flops},
+            "classes": cls,
             "nonzero_info": bad,
         }
 
-    head = results["fp64"] if "fp64" in results else results[precisions[0]]
     hp = "fp64" if "fp64" in results else precisions[0]
-    kr = head["kernel"]
-    peak = FP64_MFMA_PEAK_TFLOPS if hp == "fp64" else FP32_MFMA_PEAK_TFLOPS
-    achieved = (kr["flops"] / (kr["ms"] / 1e3) / 1e12) if kr["ms"] > 0 else None
+    head = results[hp]
+    parts = rgf.get_mixed_parts()
+    classes = class_rooflines(head["classes"], hp, parts)
+    timed = {k: v for k, v in classes.items() if v["achieved_tflops"]}
+    # the dominant kernel: the matrix-core class with the largest share of the summed kernel time
+    dom = max(timed, key=lambda k: timed[k]["share_of_kernel_time"] or 0.0) if timed else "sweep"
+    dc = classes.get(dom, {})
     lat = np.array(head["lat"])
-    # HBM bytes per launch: the counter summary is per energy, a launch covers flops / (8 Mp^3) energies
     d_mp = -(-d.M // 64) * 64
-    traffic_per_energy = measured_traffic() if hp == "fp64" else None
+    traffic_per_energy = measured_traffic() if (hp == "fp64" and dom == "sweep") else None
+    sw = head["classes"]["sweep"]
+    executed = sum(c["flops"] for c in head["classes"].values())  # every block product of the step
+    step_s = head["ms_per_step"] / 1e3
+    conv = 40.0 * d.M ** 3 * B * d.N / step_s / 1e12  # the inverse-based convention, not executed work
     out = {
         "metric": METRIC,
         "value": head["value"],
         "unit": "energy-point*layers/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": head["steps"],
+        "warmup": head["warmup"],
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "budget_s": args.budget_s,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if hp == "fp64" else "f32-mfma+f64",
         "data": "synthetic",
-        "config": {"workload": cfg.name, "layers": d.N, "block": d.M, "energies_per_step": B,
+        "config": {"workload": "c4", "layers": d.N, "block": d.M, "energies_per_step": B,
                    "energy_grid": f"linspace(-2,2,{nE})", "eta": cfg.eta, "precision": hp,
-                   "dopant_layers": len(d.shifts)},
+                   "dopant_layers": len(d.shifts), "lanes": rgf.get_tuning(d.M, hp)[1]},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": {
             "bound": "mfma",
-            "kernel": "sweep block product (zgemm role 1)",
-            "achieved": achieved,
-            "peak": peak,
+            "kernel": f"{dom}: {CLASS_NAMES[dom]}",
+            "achieved": dc.get("achieved_tflops"),
+            "peak": dc.get("peak_tflops", PEAKS["fp64"]),
             "unit": "TFLOP/s",
-            "frac": (achieved / peak) if achieved else None,
-            "traffic": (traffic_per_energy * kr["flops"] / max(1, kr["launches"]) / (8.0 * d_mp ** 3)
-                        if traffic_per_energy is not None and kr["launches"] else None),
-            "launches": kr["launches"],
-            "avg_launch_ms": kr["ms"] / max(1, kr["launches"]),
+            "frac": dc.get("frac"),
+            "traffic": (traffic_per_energy * sw["timed_flops"] / max(1, sw["timed_launches"]) / (8.0 * d_mp ** 3)
+                        if traffic_per_energy is not None and sw["timed_launches"] else None),
+            "launches": dc.get("timed_launches"),
+            "avg_launch_ms": dc.get("avg_launch_ms"),
+            "share_of_kernel_time": dc.get("share_of_kernel_time"),
+            "sampled_every": every or None,
+        },
+        "roofline_classes": classes,
+        "whole_step": {
+            "executed_block_product_flops_per_step": executed / head["steps"],
+            "achieved_tflops": executed / head["steps"] / step_s / 1e12,
+            "frac_of_fp64_peak": executed / head["steps"] / step_s / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+            "counted": "8 real flops per complex multiply-add of every block-product launch of the step, over "
+                       "the step's wall time; the panels' vector-unit elimination is not counted",
+        },
+        "convention_40M3": {
+            "tflops": conv, "frac_of_fp64_peak": conv / FP64_MFMA_PEAK_TFLOPS,
+            "note": "40 M^3 real flops per point-layer: the survey's count for the inverse-based RGF, a "
+                    "convention for comparing point-layer rates, not the work this solve-based sweep executes",
         },
         "nonzero_info": head["nonzero_info"],
     }
-    if "fp64" in results:
+    if "fp64" in results and left() > tail_s:
         # the decimation and self-energy part alone (one electrode; the device's two are the same
         # electrode, so the sweep shares one decimation): one step's energies, HIP-event timed
         Eb = E_all[:B]
@@ -498,11 +666,20 @@ def main():
                                     "sweep_and_trace": results["fp64"]["ms_per_step"] - sr_ms}
     if "mixed" in results and "fp64" in results:
         m = results["mixed"]
-        out["mixed"] = {"value": m["value"], "ms_per_step": m["ms_per_step"],
-                        "speedup_vs_fp64": m["value"] / results["fp64"]["value"]}
+        dts = [np.abs(T_by_step["mixed"][j] - T_by_step["fp64"][j]) for j in T_by_step["mixed"]
+               if j in T_by_step["fp64"]]
+        dt = np.concatenate(dts) if dts else np.array([np.nan])
+        out["mixed"] = {"value": m["value"], "ms_per_step": m["ms_per_step"], "steps": m["steps"],
+                        "warmup": m["warmup"], "speedup_vs_fp64": m["value"] / results["fp64"]["value"],
+                        "dT_vs_fp64": {"max": float(dt.max()), "p99": float(np.percentile(dt, 99)),
+                                       "mean": float(dt.mean()), "energies": int(dt.size)},
+                        "meets_1e-4": bool(dt.max() <= 1e-4),
+                        "nonzero_info": m["nonzero_info"],
+                        "roofline_classes": class_rooflines(m["classes"], "mixed", parts)}
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_seconds, max(5.0, left() - 15.0)))
+    out["wall_s"] = time.perf_counter() - START
     print(json.dumps(out), flush=True)
     return 0
 

@@ -117,6 +117,7 @@ enum {
 int rgf_transmission(const rgf_device* dev, const double* E, int64_t nE, double eta,
                      int precision, double* T, int32_t* info, void* stream);
 
+
 /*
  * rgf_transmission_batch -- the batching form: many devices of uneven block
  * size, length and energy count in one call.  devs[ndev] (host array of host
@@ -336,6 +337,46 @@ int rgf_release_workspaces(void);
 int rgf_profile(int every);
 int rgf_profile_read(int64_t* launches, double* total_ms, double* flops);
 
+/*
+ * Kernel timing by class (a breakdown of where a call's kernel time goes).
+ * rgf_profile_classes(n, mask) records, like rgf_profile, a HIP event pair
+ * around every n-th launch (counted per class) of each class whose bit
+ * (1 << RGF_PROF_*) is set in mask; rgf_profile_classes(0, 0) stops.  While
+ * either form of profiling is on, the algorithmic flops (8 real flops per
+ * complex multiply-add) and the count of EVERY block-product launch of every
+ * class are added up too, timed or not.  rgf_profile_read_class returns, for
+ * one class, the timed launches, their summed duration (ms) and flops, and
+ * the count and flops of all its launches, then resets that class.  The
+ * classes:
+ *   RGF_PROF_SWEEP      the sweep's two block products (W <- -W X and
+ *                       B' = A - L X; in the LDOS and KPM forms their main
+ *                       block products)
+ *   RGF_PROF_LU_UPDATE  trailing updates of the block LU with more than 64 rows
+ *   RGF_PROF_SOLVE      block triangular-solve updates with more than 64 rows
+ *   RGF_PROF_ROW64      64-row products (U12 blocks, diagonal-block inverses
+ *                       applied in the solves, the second pivot group's update)
+ *   RGF_PROF_PANEL      LU panel kernels (pivot search and in-panel elimination
+ *                       on the vector units; 0 flops counted)
+ *   RGF_PROF_LEAD       every product and panel of the decimation and
+ *                       self-energies
+ *   RGF_PROF_OTHER      the remaining products (final block inverse, its
+ *                       refinement, G_1N and the trace products)
+ * RGF_EINVAL for n < 0, unknown mask bits or an unknown class.
+ */
+enum {
+  RGF_PROF_SWEEP = 0,
+  RGF_PROF_LU_UPDATE = 1,
+  RGF_PROF_SOLVE = 2,
+  RGF_PROF_ROW64 = 3,
+  RGF_PROF_PANEL = 4,
+  RGF_PROF_LEAD = 5,
+  RGF_PROF_OTHER = 6,
+  RGF_PROF_COUNT = 7
+};
+int rgf_profile_classes(int every, uint32_t classes);
+int rgf_profile_read_class(int cls, int64_t* launches, double* total_ms, double* flops, int64_t* launches_all,
+                           double* flops_all);
+
 /* Tile configuration of the FP64 and mixed block products: 128 (128x128 output
  * tiles, 64-row tiles for 64-row products) or 64 (64x64 tiles).  rgf_set_tile
  * sets one tile for every size (replacing the built-in per-size choice and any
@@ -404,6 +445,18 @@ enum {
 };
 int rgf_set_mixed_parts(int parts);
 int rgf_get_mixed_parts(void);
+
+/*
+ * Decimation cap.  The Sancho-Rubio loop stops when ||alpha||_F + ||beta||_F
+ * <= 1e-14 max(1, ||D||_F) or after the cap, 100 steps by default (2^100
+ * layers, far beyond the 1/eta decay length); an energy that reaches the cap
+ * keeps its last iterate and reports RGF_INFO_SR_LEFT / RGF_INFO_SR_RIGHT.
+ * rgf_set_sr_maxit(n) lowers the cap to n in [1, 100] for later calls in the
+ * process (0 restores 100), e.g. to check the status reporting or to bound
+ * the time of a scan; RGF_EINVAL outside [0, 100].
+ */
+int rgf_set_sr_maxit(int32_t maxit);
+int rgf_get_sr_maxit(void);
 
 #ifdef __cplusplus
 }

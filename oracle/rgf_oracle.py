@@ -267,12 +267,14 @@ def transmission_block_thomas(dev, z: complex, sigma_l, sigma_r, direction: str 
 
 
 def transmission(dev, energies, eta: float, method: str = "auto", direction: str = "LR",
-                 sigma_method: str = "sancho_rubio", return_info: bool = False):
+                 sigma_method: str = "sancho_rubio", return_info: bool = False, sr_maxit: int = SR_MAXIT):
     """T(E) = Re Tr[Gamma_L G_1N Gamma_R G_1N^dagger] at each energy (eta > 0).
 
     method: "dense" (full solve), "thomas" (block-tridiagonal solve) or
-    "auto" (dense when N*M <= 600).  Returns a float64 array, and with
-    ``return_info`` also the complex traces and the decimation info.
+    "auto" (dense when N*M <= 600).  sr_maxit caps the decimation (the last
+    iterate is used, and the info reports it unconverged).  Returns a float64
+    array, and with ``return_info`` also the complex traces and the
+    decimation info.
     """
     energies = np.atleast_1d(np.asarray(energies, np.float64))
     if method == "auto":
@@ -282,7 +284,7 @@ def transmission(dev, energies, eta: float, method: str = "auto", direction: str
     infos = []
     for k, E in enumerate(energies):
         z = complex(E, eta)
-        sl, sr, info = self_energies(dev.left, dev.right, z, method=sigma_method)
+        sl, sr, info = self_energies(dev.left, dev.right, z, maxit=sr_maxit, method=sigma_method)
         out[k] = fn(dev, z, sl, sr, direction)
         infos.append(info)
     if return_info:

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
@@ -20,19 +21,30 @@ static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
 // ---------------------------------------------------------------- profiler
+// Kernel timing by class: while on, every `every`-th launch of a class in the
+// mask (counted per class) gets a HIP event pair on its own stream; the
+// algorithmic flops of every launch of every class are counted, timed or not.
+// Records are reaped without blocking (completed events only) while launches
+// go on; rgf_profile_read* wait for the rest.
 struct Profiler {
   std::mutex mu;
   bool on = false;
-  int every = 1;       // record one launch in `every`
-  int64_t seen = 0;    // launches seen while on
+  int every = 1;
+  uint32_t mask = 1u << PC_SWEEP;
   struct Rec {
     hipEvent_t a, b;
     double flops;
+    int cls;
   };
-  std::vector<Rec> recs;
+  std::deque<Rec> recs;
   std::vector<hipEvent_t> pool;
-  int64_t launches = 0;
-  double ms = 0.0, flops = 0.0;
+  struct Cls {
+    int64_t seen = 0;       // launches seen while on (sampling counter)
+    int64_t launches = 0;   // timed launches reaped
+    double ms = 0.0, flops = 0.0;
+    int64_t launches_all = 0;
+    double flops_all = 0.0;
+  } cls[PC_COUNT];
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -43,40 +55,72 @@ struct Profiler {
     RGF_HIP(hipEventCreate(&e));
     return e;
   }
+  void reap(const Rec& r) {
+    float t = 0.f;
+    RGF_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    Cls& c = cls[r.cls];
+    c.ms += t;
+    c.flops += r.flops;
+    ++c.launches;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  // completed records only, oldest first (never waits)
+  void reap_ready() {
+    while (!recs.empty()) {
+      const hipError_t q = hipEventQuery(recs.front().b);
+      if (q == hipErrorNotReady) break;
+      RGF_HIP(q);
+      reap(recs.front());
+      recs.pop_front();
+    }
+  }
   void drain() {
     for (auto& r : recs) {
       RGF_HIP(hipEventSynchronize(r.b));
-      float t = 0.f;
-      RGF_HIP(hipEventElapsedTime(&t, r.a, r.b));
-      ms += t;
-      flops += r.flops;
-      ++launches;
-      pool.push_back(r.a);
-      pool.push_back(r.b);
+      reap(r);
     }
     recs.clear();
   }
 };
 static Profiler g_prof;
 static thread_local hipEvent_t t_pending_begin = nullptr;
+static thread_local int t_prof_site = PC_OTHER;
+static thread_local bool t_prof_lead = false;
 Profiler& profiler() { return g_prof; }
 bool profiling() { return g_prof.on; }
-void profile_launch_begin(hipStream_t st) {
+ProfSite::ProfSite(int cls) : prev(t_prof_site) { t_prof_site = cls; }
+ProfSite::~ProfSite() { t_prof_site = prev; }
+ProfLead::ProfLead() : prev(t_prof_lead) { t_prof_lead = true; }
+ProfLead::~ProfLead() { t_prof_lead = prev; }
+int profile_class(int role, int rows) {
+  if (role == 1) return PC_SWEEP;
+  if (t_prof_lead) return PC_LEAD;
+  if (rows == LU_NB) return PC_ROW64;
+  return t_prof_site;
+}
+int profile_panel_class() { return t_prof_lead ? PC_LEAD : PC_PANEL; }
+void profile_launch_begin(hipStream_t st, int cls) {
+  t_pending_begin = nullptr;
+  if (!g_prof.on) return;
   std::lock_guard<std::mutex> lk(g_prof.mu);
-  if (g_prof.seen++ % g_prof.every != 0) {  // not sampled
-    t_pending_begin = nullptr;
-    return;
-  }
+  if (!g_prof.on || !(g_prof.mask & (1u << cls))) return;
+  if (g_prof.cls[cls].seen++ % g_prof.every != 0) return;  // not sampled
   t_pending_begin = g_prof.get();
   RGF_HIP(hipEventRecord(t_pending_begin, st));
 }
-void profile_launch_end(hipStream_t st, double flops) {
+void profile_launch_end(hipStream_t st, int cls, double flops) {
+  if (!g_prof.on) return;
   std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.cls[cls].flops_all += flops;
+  ++g_prof.cls[cls].launches_all;
   if (!t_pending_begin) return;
   hipEvent_t e = g_prof.get();
   RGF_HIP(hipEventRecord(e, st));
-  g_prof.recs.push_back({t_pending_begin, e, flops});
-  if (g_prof.recs.size() > 4096) g_prof.drain();
+  g_prof.recs.push_back({t_pending_begin, e, flops, cls});
+  t_pending_begin = nullptr;
+  if (g_prof.recs.size() > 1024) g_prof.reap_ready();
+  if (g_prof.recs.size() > 65536) g_prof.drain();  // bound the event pool
 }
 
 // ------------------------------------------------------------- tuning table
@@ -98,6 +142,8 @@ int tile_for(int prec, int Mp) {
 }
 static int g_mixed_parts = RGF_MIXED_ALL;
 int mixed_parts() { return g_mixed_parts; }
+static std::atomic<int> g_sr_maxit{SR_MAXIT};
+int sr_maxit() { return g_sr_maxit.load(); }
 
 // -------------------------------------------------------------- workspaces
 struct Workspace {
@@ -109,6 +155,18 @@ static std::mutex g_ws_mu;
 static std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 
 static void drop_graphs_on(const void* base);
+
+// One call at a time enqueues into the workspace of a (device, stream): two
+// host threads calling on the same stream would otherwise share one arena
+// (and a reallocation by one could free memory the other has enqueued work
+// into).  The lock is held while a call enqueues its work, not until it runs;
+// the stream orders the executions.
+static std::mutex g_call_mu;
+static std::map<std::pair<int, hipStream_t>, std::mutex> g_call_locks;
+static std::mutex& stream_call_mutex(int dev, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_call_mu);
+  return g_call_locks[{dev, st}];
+}
 
 static Workspace& workspace(int dev, hipStream_t st, size_t need) {
   std::lock_guard<std::mutex> lk(g_ws_mu);
@@ -293,7 +351,7 @@ SmallArgs small_args(const rgf_device& d, const double* E, int64_t nE, double et
   a.T = T;
   a.info = info;
   a.sr_tol = SR_TOL;
-  a.sr_maxit = SR_MAXIT;
+  a.sr_maxit = sr_maxit();
   a.u_l = 0.0;
   a.u_r = 0.0;
   return a;
@@ -308,9 +366,14 @@ SmallArgs small_args(const rgf_device& d, const double* E, int64_t nE, double et
 // captured arguments stay valid for any energies and output buffers.  The
 // sweep records no memset, only kernels.  Decimation stays eager: its
 // iteration count depends on the data.
+// Everything the captured kernels read as an argument is part of the key: the
+// block addresses, the shape, the product configuration, eta (formed into
+// every operator block) and whether the two electrodes share one decimation
+// (which done-flags the trace reads).
 struct GraphKey {
   const void *Hd, *Hu, *Sd, *Su, *lH01, *lS01, *rH01, *rS01;
-  int N, M, B, prec, parts, tile;
+  int N, M, B, prec, parts, tile, same;
+  uint64_t eta_bits;
   const void* base;
   hipStream_t st;
   bool operator<(const GraphKey& o) const {
@@ -358,7 +421,7 @@ static void drop_graphs_on(const void* base) {
 }
 
 // Replay (capturing on first use) the sweep of `eng` on stream `ls`.
-static void sweep_graph(Engine& eng, const rgf_device& d, bool same, int B, int prec, char* base,
+static void sweep_graph(Engine& eng, const rgf_device& d, bool same, double eta, int B, int prec, char* base,
                         const Layout& lay, hipStream_t ls) {
   GraphKey k;
   std::memset(&k, 0, sizeof(k));
@@ -376,6 +439,8 @@ static void sweep_graph(Engine& eng, const rgf_device& d, bool same, int B, int 
   k.prec = prec;
   k.parts = mixed_parts();
   k.tile = tile_for(prec, lay.Mp);
+  k.same = same ? 1 : 0;
+  std::memcpy(&k.eta_bits, &eta, sizeof(double));
   k.base = base;
   k.st = ls;
   std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -408,51 +473,59 @@ static void sweep_graph(Engine& eng, const rgf_device& d, bool same, int B, int 
   RGF_HIP(hipGraphLaunch(it->second.ex, ls));
 }
 
-// Energies [lo, hi) of one device on one stream, in chunks of at most `chunk`.
-static void run_range(const rgf_device& d, const double* E, int64_t lo, int64_t hi, double eta, int precision,
-                      double* T, int32_t* info, int chunk, hipStream_t ls, double u_l, double u_r,
-                      const Grouping& grp) {
-  const int M = d.M;
-  const int Mp = (int)round_up(M, 64);
+// One energy chunk [e0, e0 + B) of one device through the whole path on stream
+// ls, in the arena `base` laid out as `lay` (lay.batch == B).
+static void run_chunk(const rgf_device& d, const double* E, int64_t e0, int B, double eta, int precision,
+                      double* T, int32_t* info, char* base, const Layout& lay, int32_t* host_active, bool graphs,
+                      hipStream_t ls, double u_l, double u_r, const Grouping& grp) {
   // one decimation serves both sides only for the same electrode at the same shift
   const bool same = same_lead(d.left, d.right) && u_l == u_r;
   const bool biased = u_l != 0.0 || u_r != 0.0;
   const int prec = precision == RGF_MIXED ? PREC_F32 : PREC_F64;
+  const double* Ec = E + e0;
+  if (graphs) {  // stage the energies at a stable address
+    double* Ew = reinterpret_cast<double*>(base + lay.energies);
+    RGF_HIP(hipMemcpyAsync(Ew, Ec, sizeof(double) * B, hipMemcpyDeviceToDevice, ls));
+    Ec = Ew;
+  }
+  Engine eng(base, lay, ls, prec, d.M, Ec, eta, host_active);
+  if (grp.per > 0) eng.set_group(grp.per, e0, grp.stride);
+  if (biased) {  // a rigidly shifted electrode is the unshifted one at E - u
+    double* El = reinterpret_cast<double*>(base + lay.elead);
+    double* Er = reinterpret_cast<double*>(base + lay.erlead);
+    launch_shift(El, Ec, B, u_l, ls);
+    launch_shift(Er, Ec, B, u_r, ls);
+    eng.set_lead_energies(El, Er);
+  }
+  eng.decimate(d.left, eng.done_l(), true);
+  eng.self_energy(d.left, true, eng.sigL());
+  if (!same) eng.decimate(d.right, eng.done_r(), false);
+  eng.self_energy(d.right, false, eng.sigR());
+  eng.broadenings();
+  if (graphs) {
+    sweep_graph(eng, d, same, eta, B, prec, base, lay, ls);
+    RGF_HIP(hipMemcpyAsync(T + e0, base + lay.tout, sizeof(double) * B, hipMemcpyDeviceToDevice, ls));
+    if (info)
+      RGF_HIP(hipMemcpyAsync(info + e0, base + lay.iout, sizeof(int32_t) * B, hipMemcpyDeviceToDevice, ls));
+  } else {
+    eng.sweep_and_trace(d, T + e0, info ? info + e0 : nullptr, same);
+  }
+}
+
+// Energies [lo, hi) of one device on one stream, in chunks of at most `chunk`.
+static void run_range(const rgf_device& d, const double* E, int64_t lo, int64_t hi, double eta, int precision,
+                      double* T, int32_t* info, int chunk, hipStream_t ls, double u_l, double u_r,
+                      const Grouping& grp) {
+  const int Mp = (int)round_up(d.M, 64);
   const bool graphs = graphs_enabled() && grp.per == 0;  // a captured sweep keys on one device
   int dev = 0;
   RGF_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> call(stream_call_mutex(dev, ls));
   for (int64_t e0 = lo; e0 < hi;) {
     const int B = (int)std::min<int64_t>(chunk, hi - e0);
     const Layout lay = Layout::make(Mp, B);
     Workspace& w = workspace(dev, ls, lay.bytes);
-    const double* Ec = E + e0;
-    if (graphs) {  // stage the energies at a stable address
-      double* Ew = reinterpret_cast<double*>(w.base + lay.energies);
-      RGF_HIP(hipMemcpyAsync(Ew, Ec, sizeof(double) * B, hipMemcpyDeviceToDevice, ls));
-      Ec = Ew;
-    }
-    Engine eng(w.base, lay, ls, prec, M, Ec, eta, w.host_active);
-    if (grp.per > 0) eng.set_group(grp.per, e0, grp.stride);
-    if (biased) {  // a rigidly shifted electrode is the unshifted one at E - u
-      double* El = reinterpret_cast<double*>(w.base + lay.elead);
-      double* Er = reinterpret_cast<double*>(w.base + lay.erlead);
-      launch_shift(El, Ec, B, u_l, ls);
-      launch_shift(Er, Ec, B, u_r, ls);
-      eng.set_lead_energies(El, Er);
-    }
-    eng.decimate(d.left, eng.done_l(), true);
-    eng.self_energy(d.left, true, eng.sigL());
-    if (!same) eng.decimate(d.right, eng.done_r(), false);
-    eng.self_energy(d.right, false, eng.sigR());
-    eng.broadenings();
-    if (graphs) {
-      sweep_graph(eng, d, same, B, prec, w.base, lay, ls);
-      RGF_HIP(hipMemcpyAsync(T + e0, w.base + lay.tout, sizeof(double) * B, hipMemcpyDeviceToDevice, ls));
-      if (info)
-        RGF_HIP(hipMemcpyAsync(info + e0, w.base + lay.iout, sizeof(int32_t) * B, hipMemcpyDeviceToDevice, ls));
-    } else {
-      eng.sweep_and_trace(d, T + e0, info ? info + e0 : nullptr, same);
-    }
+    run_chunk(d, E, e0, B, eta, precision, T, info, w.base, lay, w.host_active, graphs, ls, u_l, u_r, grp);
     e0 += B;
   }
 }
@@ -654,6 +727,7 @@ static void ldos_range(const rgf_device& d, const double* E, int64_t lo, int64_t
   const bool same = same_lead(d.left, d.right);
   int dev = 0;
   RGF_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> call(stream_call_mutex(dev, st));
   const int64_t out_per = (int64_t)N * M;
   for (int64_t e0 = lo; e0 < hi;) {
     const int B = (int)std::min<int64_t>(chunk, hi - e0);
@@ -724,6 +798,7 @@ void self_energy_impl(const rgf_lead& lead, int side, const double* E, int64_t n
   const int Mp = (int)round_up(M, 64);
   int dev = 0;
   RGF_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> call(stream_call_mutex(dev, st));
   for (int64_t e0 = 0; e0 < nE;) {
     const int B = chunk_for(Mp, nE - e0);
     const Layout lay = Layout::make(Mp, B);
@@ -872,27 +947,38 @@ int rgf_release_workspaces(void) {
   });
 }
 
-int rgf_profile(int every) {
+int rgf_profile(int every) { return rgf_profile_classes(every, 1u << RGF_PROF_SWEEP); }
+
+int rgf_profile_classes(int every, uint32_t classes) {
   return guarded([&] {
     RGF_CHECK(every >= 0, RGF_EINVAL, "rgf_profile: negative sampling period");
+    RGF_CHECK((classes & ~((1u << PC_COUNT) - 1)) == 0, RGF_EINVAL, "rgf_profile_classes: unknown class bits");
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.on = every != 0;
     g_prof.every = every > 0 ? every : 1;
-    g_prof.seen = 0;
+    g_prof.mask = classes;
+    for (auto& c : g_prof.cls) c.seen = 0;
+  });
+}
+
+int rgf_profile_read_class(int cls, int64_t* launches, double* total_ms, double* flops, int64_t* launches_all,
+                           double* flops_all) {
+  return guarded([&] {
+    RGF_CHECK(cls >= 0 && cls < PC_COUNT, RGF_EINVAL, "rgf_profile_read_class: unknown class");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.drain();
+    Profiler::Cls& c = g_prof.cls[cls];
+    if (launches) *launches = c.launches;
+    if (total_ms) *total_ms = c.ms;
+    if (flops) *flops = c.flops;
+    if (launches_all) *launches_all = c.launches_all;
+    if (flops_all) *flops_all = c.flops_all;
+    c = Profiler::Cls();
   });
 }
 
 int rgf_profile_read(int64_t* launches, double* total_ms, double* flops) {
-  return guarded([&] {
-    std::lock_guard<std::mutex> lk(g_prof.mu);
-    g_prof.drain();
-    if (launches) *launches = g_prof.launches;
-    if (total_ms) *total_ms = g_prof.ms;
-    if (flops) *flops = g_prof.flops;
-    g_prof.launches = 0;
-    g_prof.ms = 0.0;
-    g_prof.flops = 0.0;
-  });
+  return rgf_profile_read_class(RGF_PROF_SWEEP, launches, total_ms, flops, nullptr, nullptr);
 }
 
 int rgf_set_mixed_parts(int parts) {
@@ -903,6 +989,15 @@ int rgf_set_mixed_parts(int parts) {
 }
 
 int rgf_get_mixed_parts(void) { return g_mixed_parts; }
+
+int rgf_set_sr_maxit(int32_t maxit) {
+  return guarded([&] {
+    RGF_CHECK(maxit >= 0 && maxit <= SR_MAXIT, RGF_EINVAL, "decimation cap must be in [0, 100]");
+    g_sr_maxit = maxit ? maxit : SR_MAXIT;
+  });
+}
+
+int rgf_get_sr_maxit(void) { return g_sr_maxit.load(); }
 
 int rgf_get_tile(int precision, int32_t* tile) {
   return guarded([&] {

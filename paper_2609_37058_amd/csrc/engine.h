@@ -9,14 +9,13 @@
 namespace rgf {
 
 constexpr double SR_TOL = 1e-14;
-constexpr int SR_MAXIT = 100;
+constexpr int SR_MAXIT = 100;  // decimation cap (2^100 layers, far beyond 1/eta)
+// the cap in effect: SR_MAXIT unless lowered by rgf_set_sr_maxit
+int sr_maxit();
 constexpr int32_t SING_LEAD = 0x1000000;  // stored code; decodes to layer field 0xFFFFFF
 
 struct Profiler;
 Profiler& profiler();
-void profile_launch_begin(hipStream_t st);
-void profile_launch_end(hipStream_t st, double flops);
-bool profiling();
 
 constexpr int MAX_M = 2048;  // largest block size the library accepts
 

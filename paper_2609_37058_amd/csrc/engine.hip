@@ -119,17 +119,11 @@ MatRef Engine::mref(z64* p, int64_t ld, int64_t bstride, const int32_t* ridx) co
 }
 
 double Engine::gemm(GemmArgs g, int prec, bool timed) {
-  const int role = timed ? 1 : 0;
-  if (timed && profiling()) {
-    profile_launch_begin(st_);
-    double f = launch_gemm(g, prec, tile_for(prec, Mp_), st_, role);
-    profile_launch_end(st_, f);
-    return f;
-  }
-  return launch_gemm(g, prec, tile_for(prec, Mp_), st_, role);
+  return launch_gemm(g, prec, tile_for(prec, Mp_), st_, timed ? 1 : 0);
 }
 
 void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
+  ProfLead lead_scope;
   const int Mp = Mp_;
   const double* El = left ? EL_ : ER_;
   const int tile = tile_for(PREC_F64, Mp_);
@@ -152,7 +146,8 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
   launch_fill(f, B_, st_);
   launch_frob_scale(mref(eps_, Mp, MM_), M_, M_, scale_, B_, st_);
 
-  for (int it = 1; it <= SR_MAXIT; ++it) {
+  const int maxit = sr_maxit();
+  for (int it = 1; it <= maxit; ++it) {
     // [Xa Xb] = eps^-1 [alpha beta]
     FillArgs c = fill_args(mref(Tsr_, Mp, MM_), Mp, Mp, FILL_MAT);
     c.src = mref(eps_, Mp, MM_);
@@ -187,7 +182,7 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
     launch_sr_update(u, B_, st_);
     RGF_HIP(hipMemsetAsync(active_, 0, sizeof(int32_t), st_));
     launch_sr_check(partial_, nblk_sr_, scale_, SR_TOL, it, done, iters_, active_, B_, st_);
-    if ((it >= 12 && it % 4 == 0) || it == SR_MAXIT) {
+    if ((it >= 12 && it % 4 == 0) || it == maxit) {
       RGF_HIP(hipMemcpyAsync(host_active_, active_, sizeof(int32_t), hipMemcpyDeviceToHost, st_));
       RGF_HIP(hipStreamSynchronize(st_));
       if (*host_active_ == 0) break;
@@ -196,6 +191,7 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
 }
 
 void Engine::self_energy(const rgf_lead& lead, bool left, z64* out) {
+  ProfLead lead_scope;
   const int Mp = Mp_;
   const int tile = tile_for(PREC_F64, Mp_);
   FillArgs f = fill_args(mref(Tsr_, Mp, MM_), Mp, Mp, FILL_MAT);

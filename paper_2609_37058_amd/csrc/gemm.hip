@@ -330,10 +330,15 @@ double launch_gemm(const GemmArgs& g, int prec, int tile, hipStream_t st, int ro
   if (g.rows <= 0 || g.cols <= 0 || g.batch <= 0) return 0.0;
   RGF_CHECK(g.K % BK == 0, RGF_EINVAL, "gemm: K not a multiple of 16");
   RGF_CHECK(g.rows % 64 == 0 && g.cols % 64 == 0, RGF_EINVAL, "gemm: shape not tiled");
+  const double flops = 8.0 * g.rows * (double)g.cols * g.K * g.batch;
+  const bool prof = profiling();
+  const int cls = prof ? profile_class(role, g.rows) : 0;
+  if (prof) profile_launch_begin(st, cls);
   if (prec == PREC_F64) launch_prec<double>(g, tile, st, role);
   else launch_prec<float>(g, tile, st, role);
   RGF_HIP(hipGetLastError());
-  return 8.0 * g.rows * (double)g.cols * g.K * g.batch;
+  if (prof) profile_launch_end(st, cls, flops);
+  return flops;
 }
 
 }  // namespace rgf

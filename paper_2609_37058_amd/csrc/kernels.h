@@ -76,6 +76,41 @@ inline GemmArgs gemm_args(int rows, int cols, int K, int batch, const int32_t* s
   return g;
 }
 
+// ------------------------------------------------------- kernel timing
+// Classes of launches for the kernel-time breakdown (rgf_profile_classes);
+// the values are the RGF_PROF_* bits of the C ABI.
+enum {
+  PC_SWEEP = RGF_PROF_SWEEP,
+  PC_LU_UPDATE = RGF_PROF_LU_UPDATE,
+  PC_SOLVE = RGF_PROF_SOLVE,
+  PC_ROW64 = RGF_PROF_ROW64,
+  PC_PANEL = RGF_PROF_PANEL,
+  PC_LEAD = RGF_PROF_LEAD,
+  PC_OTHER = RGF_PROF_OTHER,
+  PC_COUNT = RGF_PROF_COUNT
+};
+bool profiling();
+// event pair around one launch on `st` when its class is sampled; end() also
+// counts the launch's algorithmic flops (timed or not) while profiling is on
+void profile_launch_begin(hipStream_t st, int cls);
+void profile_launch_end(hipStream_t st, int cls, double flops);
+// the class of a block product of `rows` output rows with kernel role `role`, and of an LU panel,
+// given the calling thread's site and phase
+int profile_class(int role, int rows);
+int profile_panel_class();
+// Scope guards (thread-local): products launched inside belong to `cls` (unless they are
+// role-1 or 64-row products), or, inside a lead scope, to the decimation and self-energies.
+struct ProfSite {
+  explicit ProfSite(int cls);
+  ~ProfSite();
+  int prev;
+};
+struct ProfLead {
+  ProfLead();
+  ~ProfLead();
+  bool prev;
+};
+
 // tile = 64 or 128 (square output tiles); role 1 marks the sweep's main block
 // products (a separate kernel symbol, so profiles can single them out).
 // Returns the algorithmic flops launched.

@@ -160,15 +160,7 @@ __global__ void kpm_dos_kernel(const double* mu, int nm, double a, double b, con
 }
 
 // the Chebyshev step's products, timed per launch when profiling is on
-void timed_gemm(const GemmArgs& g, hipStream_t st) {
-  if (profiling()) {
-    profile_launch_begin(st);
-    const double f = launch_gemm(g, PREC_F64, KPM_TILE, st, 1);
-    profile_launch_end(st, f);
-  } else {
-    launch_gemm(g, PREC_F64, KPM_TILE, st, 1);
-  }
-}
+void timed_gemm(const GemmArgs& g, hipStream_t st) { launch_gemm(g, PREC_F64, KPM_TILE, st, 1); }
 
 // Chunks of the inner dimension for a sweep step: enough (Mp/64 x Rp/64 x nc)
 // workgroups to fill the chip, nc dividing Mp / 16.

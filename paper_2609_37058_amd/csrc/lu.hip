@@ -264,12 +264,13 @@ __global__ __launch_bounds__(512) void lu_panel_kernel(LuPanelArgs a) {
       // wavefront that owns the winning row: the lowest lane holding it (lane w = wavefront w)
       const unsigned long long wmask = __ballot(lane < nwaves && wr == gi);
       const int gw = wmask ? (int)__builtin_ctzll(wmask) : 0;
-      const double gb = __longlong_as_double((long long)(gk - 1ull));
       const int p = (gi < Mp) ? gi : 0;  // a square system always has a candidate left
       const z64* u = slot[buf][gw];  // the pivot row's sub-panel entries (LDS broadcast reads)
       if (tid == 0) {
         piv[cb + j] = p;
-        if (!(gb > 0.0)) sh_sing = 1;
+        // key 1 is an exact zero (|Re|+|Im| = +0); a NaN pivot has the largest key and is not
+        // a zero pivot: it reaches T, which reports it as non-finite
+        if (gk <= 1ull) sh_sing = 1;
       }
       // ---- the pivot row leaves the candidates; its entries are U (t >= j) and L (t < j) ----
 #pragma clang loop unroll(full)
@@ -386,6 +387,9 @@ void launch_lu_panel(const LuPanelArgs& a, int batch, hipStream_t st) {
   RGF_CHECK(a.Mp % 64 == 0 && a.Mp <= MAXMP, RGF_EINVAL, "lu panel: Mp must be a multiple of 64, <= 2048");
   // whole wavefronts only: the butterflies and the per-wavefront slots assume full waves
   auto threads = [&](int rpt) { return (unsigned)round_up((a.Mp + rpt - 1) / rpt, 64); };
+  const bool prof = profiling();
+  const int cls = prof ? profile_panel_class() : 0;
+  if (prof) profile_launch_begin(st, cls);
   if (a.Mp <= 512) {
     hipLaunchKernelGGL((lu_panel_kernel<1, 16>), dim3(batch), dim3(threads(1)), 0, st, a);
   } else if (a.Mp <= 1024) {
@@ -394,6 +398,7 @@ void launch_lu_panel(const LuPanelArgs& a, int batch, hipStream_t st) {
     hipLaunchKernelGGL((lu_panel_kernel<4, 8>), dim3(batch), dim3(threads(4)), 0, st, a);
   }
   RGF_HIP(hipGetLastError());
+  if (prof) profile_launch_end(st, cls, 0.0);
 }
 
 }  // namespace rgf

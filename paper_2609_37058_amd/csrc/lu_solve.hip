@@ -24,6 +24,7 @@ namespace rgf {
 
 void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int32_t* skip, int32_t code,
                int prec, int tile, hipStream_t st) {
+  ProfSite site(PC_LU_UPDATE);
   const int64_t inv_bs = (int64_t)64 * Mp;
   {  // every row starts as a pivot candidate
     FillArgs f = fill_args(nomat(), 0, 0, FILL_ZERO);
@@ -124,6 +125,7 @@ static void diag(GemmArgs base, z64* Yrows, const z64* D, int64_t inv_bs, int64_
 
 void lu_solve(const LuBufs& g, z64* T, int64_t bs, int Mp, z64* Y, int64_t ybs, int nrhs, int batch,
               const int32_t* skip, int prec, int tile, hipStream_t st) {
+  ProfSite site(PC_SOLVE);
   // Blocks of two panels (128 rows): one product over the whole inner dimension on
   // 128-row tiles, then the 2 x 2 block triangle with 64-row products.
   const int64_t inv_bs = (int64_t)64 * Mp;

@@ -77,6 +77,10 @@ __device__ bool gje(int M, int nr, z64* Wk) {
     int idx = 0x7fffffff;
     if (lane >= j && lane < M) {
       v = zabs1(Wk[lane * ld + j]);
+      // a NaN entry ranks above every number (as the batched panel's integer key does), so
+      // the butterfly below leaves one winner in every lane and only an exact zero column
+      // counts as a singular pivot; the NaN then reaches T, which reports it as non-finite
+      if (v != v) v = __builtin_inf();
       idx = lane;
     }
     for (int off = 32; off > 0; off >>= 1) {

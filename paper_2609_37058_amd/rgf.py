@@ -71,6 +71,11 @@ SIGNATURES = {
     "rgf_set_checks": (C.c_int, [C.c_int]),
     "rgf_get_checks": (C.c_int, []),
     "rgf_profile_read": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "rgf_profile_classes": (C.c_int, [C.c_int, C.c_uint32]),
+    "rgf_set_sr_maxit": (C.c_int, [C.c_int32]),
+    "rgf_get_sr_maxit": (C.c_int, []),
+    "rgf_profile_read_class": (C.c_int, [C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "rgf_get_tile": (C.c_int, [C.c_int, C.POINTER(C.c_int32)]),
     "rgf_set_mixed_parts": (C.c_int, [C.c_int]),
     "rgf_get_mixed_parts": (C.c_int, []),
@@ -124,14 +129,27 @@ def _check(rc: int):
         raise RgfError(rc, load().rgf_last_error().decode())
 
 
-def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+def _ptr(t: Optional[torch.Tensor], dtype: Optional[torch.dtype] = None, what: str = "tensor") -> Optional[int]:
+    """Device address of a contiguous CUDA tensor, checked against the dtype the C call reads or
+    writes through it (a float32 energy grid read as float64 would be an out-of-bounds access)."""
     if t is None:
         return None
     if not t.is_cuda:
-        raise ValueError("librgf takes device tensors")
+        raise ValueError(f"librgf takes device tensors ({what} is on {t.device})")
     if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
     return t.data_ptr()
+
+
+_F64, _I32, _C128 = torch.float64, torch.int32, torch.complex128
+
+
+def _energies(E: torch.Tensor) -> torch.Tensor:
+    if not isinstance(E, torch.Tensor) or E.dtype != _F64:
+        raise ValueError(f"energies must be a float64 device tensor, got {getattr(E, 'dtype', type(E))}")
+    return E.contiguous()
 
 
 def _stream(stream) -> Optional[int]:
@@ -153,7 +171,12 @@ class LeadTensors:
         return self.H00.shape[-1]
 
     def cstruct(self) -> rgf_lead:
-        return rgf_lead(self.M, _ptr(self.H00), _ptr(self.H01), _ptr(self.S00), _ptr(self.S01))
+        for name in ("H00", "H01", "S00", "S01"):
+            t = getattr(self, name)
+            if t.shape != (self.M, self.M):
+                raise ValueError(f"lead {name} must be {self.M} x {self.M}, got {tuple(t.shape)}")
+        return rgf_lead(self.M, _ptr(self.H00, _C128, "H00"), _ptr(self.H01, _C128, "H01"),
+                        _ptr(self.S00, _C128, "S00"), _ptr(self.S01, _C128, "S01"))
 
 
 @dataclass
@@ -175,9 +198,14 @@ class DeviceTensors:
         return self.Hd.shape[-1]
 
     def cstruct(self) -> rgf_device:
-        hu = _ptr(self.Hu) if self.Hu.numel() else None
-        su = _ptr(self.Su) if self.Su.numel() else None
-        return rgf_device(self.N, self.M, _ptr(self.Hd), hu, _ptr(self.Sd), su,
+        N, M = self.N, self.M
+        for name, n in (("Hd", N), ("Sd", N), ("Hu", N - 1), ("Su", N - 1)):
+            t = getattr(self, name)
+            if tuple(t.shape) != (n, M, M) and not (n == 0 and t.numel() == 0):
+                raise ValueError(f"{name} must be [{n}, {M}, {M}], got {tuple(t.shape)}")
+        hu = _ptr(self.Hu, _C128, "Hu") if self.Hu.numel() else None
+        su = _ptr(self.Su, _C128, "Su") if self.Su.numel() else None
+        return rgf_device(N, M, _ptr(self.Hd, _C128, "Hd"), hu, _ptr(self.Sd, _C128, "Sd"), su,
                           self.left.cstruct(), self.right.cstruct())
 
 
@@ -189,23 +217,34 @@ def transmission(dev: DeviceTensors, E: torch.Tensor, eta: float, precision="fp6
     Stream-ordered like the C call: synchronise the stream before reading T.
     """
     lib = load()
-    E = E.contiguous()
+    E = _energies(E)
     nE = E.numel()
     if out is None:
         out = torch.empty(nE, dtype=torch.float64, device=E.device)
     if info is None:
         info = torch.empty(nE, dtype=torch.int32, device=E.device)
+    if out.numel() < nE or info.numel() < nE:
+        raise ValueError("out and info need one element per energy")
     d = dev.cstruct()
-    _check(lib.rgf_transmission(C.byref(d), _ptr(E), nE, float(eta), PRECISION[precision], _ptr(out),
-                                _ptr(info), _stream(stream)))
+    _check(lib.rgf_transmission(C.byref(d), _ptr(E, _F64, "E"), nE, float(eta), PRECISION[precision],
+                                _ptr(out, _F64, "out"), _ptr(info, _I32, "info"), _stream(stream)))
     return out, info
+
+
+def set_sr_maxit(maxit: int):
+    """Cap the decimation at `maxit` steps (1..100) for later calls; 0 restores the default 100."""
+    _check(load().rgf_set_sr_maxit(int(maxit)))
+
+
+def get_sr_maxit() -> int:
+    return int(load().rgf_get_sr_maxit())
 
 
 def transmission_bias(dev: DeviceTensors, E: torch.Tensor, eta: float, u_left: float, u_right: float,
                       precision="fp64", stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
     """T(E, V_b) with the zero-bias device and electrodes rigidly shifted by u_left / u_right (eV)."""
     lib = load()
-    E = E.contiguous()
+    E = _energies(E)
     nE = E.numel()
     out = torch.empty(nE, dtype=torch.float64, device=E.device)
     info = torch.empty(nE, dtype=torch.int32, device=E.device)
@@ -218,7 +257,7 @@ def transmission_bias(dev: DeviceTensors, E: torch.Tensor, eta: float, u_left: f
 def ldos(dev: DeviceTensors, E: torch.Tensor, eta: float, parts=("dos", "left", "right"), stream=None):
     """Orbital-resolved LDOS: (dos, ados_left, ados_right, info), each [nE, N, M] (None when not in parts)."""
     lib = load()
-    E = E.contiguous()
+    E = _energies(E)
     nE = E.numel()
     N, M = dev.N, dev.M
     unknown = set(parts) - {"dos", "left", "right"}
@@ -251,6 +290,7 @@ def kpm_fermi(mu: torch.Tensor, e_min: float, e_max: float, n_states: float, str
     """The Fermi level (a one-element device tensor) at which the Jackson-smoothed state count is n_states."""
     lib = load()
     mu = mu.contiguous()
+    _ptr(mu, _F64, "mu")
     ef = torch.empty(1, dtype=torch.float64, device=mu.device)
     _check(lib.rgf_kpm_fermi(_ptr(mu), mu.numel(), float(e_min), float(e_max), float(n_states), _ptr(ef),
                              _stream(stream)))
@@ -260,7 +300,8 @@ def kpm_fermi(mu: torch.Tensor, e_min: float, e_max: float, n_states: float, str
 def kpm_dos(mu: torch.Tensor, e_min: float, e_max: float, E: torch.Tensor, stream=None) -> torch.Tensor:
     """Jackson-smoothed density of states per unit energy at the energies E."""
     lib = load()
-    mu, E = mu.contiguous(), E.contiguous()
+    mu, E = mu.contiguous(), _energies(E)
+    _ptr(mu, _F64, "mu")
     out = torch.empty(E.numel(), dtype=torch.float64, device=E.device)
     _check(lib.rgf_kpm_dos(_ptr(mu), mu.numel(), float(e_min), float(e_max), _ptr(E), E.numel(), _ptr(out),
                            _stream(stream)))
@@ -271,8 +312,9 @@ def landauer_current(E: torch.Tensor, T: torch.Tensor, mu_left: float, mu_right:
                      stream=None) -> torch.Tensor:
     """I (amperes, a one-element device tensor) = G0 * trapezoid of (f_L - f_R) T over the ascending E."""
     lib = load()
-    E = E.contiguous()
+    E = _energies(E)
     T = T.contiguous()
+    _ptr(T, _F64, "T")
     if E.numel() != T.numel():
         raise ValueError("E and T differ in length")
     I = torch.empty(1, dtype=torch.float64, device=E.device)
@@ -303,7 +345,7 @@ def transmission_kmesh(images, R, kpts, weights, E: torch.Tensor, eta: float, pr
     nR, nk = len(R), len(kpts)
     if len(images) != nR or len(weights) != nk:
         raise ValueError("one image per lattice vector and one weight per k-point")
-    E = E.contiguous()
+    E = _energies(E)
     nE = E.numel()
     T = torch.empty(nE, dtype=torch.float64, device=E.device)
     Tk = torch.empty((nk, nE), dtype=torch.float64, device=E.device)
@@ -326,7 +368,7 @@ def transmission_batch(devs, Es, eta: float, precision="fp64", stream=None):
     n = len(devs)
     if len(Es) != n:
         raise ValueError("one energy tensor per device")
-    Es = [E.contiguous() for E in Es]
+    Es = [_energies(E) for E in Es]
     outs = [torch.empty(E.numel(), dtype=torch.float64, device=E.device) for E in Es]
     infos = [torch.empty(E.numel(), dtype=torch.int32, device=E.device) for E in Es]
     cdevs = (rgf_device * max(n, 1))(*[d.cstruct() for d in devs])
@@ -344,7 +386,7 @@ def lead_self_energy(lead: LeadTensors, side: int, E: torch.Tensor, eta: float, 
                      stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Sigma[nE, M, M] of one lead (side RGF_LEFT: L g_L U, RGF_RIGHT: U g_R L) and info."""
     lib = load()
-    E = E.contiguous()
+    E = _energies(E)
     nE = E.numel()
     sigma = torch.empty((nE, lead.M, lead.M), dtype=torch.complex128, device=E.device)
     info = torch.empty(nE, dtype=torch.int32, device=E.device)
@@ -388,6 +430,29 @@ def profile_read() -> Tuple[int, float, float]:
     fl = C.c_double()
     _check(load().rgf_profile_read(C.byref(n), C.byref(ms), C.byref(fl)))
     return n.value, ms.value, fl.value
+
+
+#: kernel classes of rgf_profile_classes (include/rgf.h, RGF_PROF_*)
+PROFILE_CLASSES = ("sweep", "lu_update", "solve", "row64", "panel", "lead", "other")
+
+
+def profile_classes(enable: bool, every: int = 1, classes=PROFILE_CLASSES):
+    """Time every `every`-th launch of each named kernel class; count the flops of all launches."""
+    mask = 0
+    for c in classes:
+        mask |= 1 << PROFILE_CLASSES.index(c)
+    _check(load().rgf_profile_classes(int(every) if enable else 0, mask if enable else 0))
+
+
+def profile_read_classes() -> dict:
+    """{class: {timed launches, ms, timed flops, launches, flops}} for every class; resets them."""
+    out = {}
+    for i, name in enumerate(PROFILE_CLASSES):
+        n, ms, fl, na, fa = C.c_int64(), C.c_double(), C.c_double(), C.c_int64(), C.c_double()
+        _check(load().rgf_profile_read_class(i, C.byref(n), C.byref(ms), C.byref(fl), C.byref(na), C.byref(fa)))
+        out[name] = {"timed_launches": n.value, "ms": ms.value, "timed_flops": fl.value,
+                     "launches": na.value, "flops": fa.value}
+    return out
 
 
 def get_tile(precision="fp64") -> int:

@@ -272,6 +272,26 @@ class Request:
     lead_key: int
 
 
+def phase_vectors(n: int, R: int, seed: int) -> np.ndarray:
+    """R random-phase vectors of length n (columns; E[r r^dagger] = I), the KPM trace estimator's
+    inputs: entries exp(2 pi i u), u uniform on [0, 1) from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    return np.exp(2j * np.pi * rng.random((n, R)))
+
+
+def kpm_bounds(layer: Lead, shifts: Optional[Dict[int, float]] = None, margin: float = 1.01):
+    """Spectral bounds +-e for a device repeating `layer` with on-site shifts: |e| <= ||H||_2 /
+    lambda_min(S) with ||H||_2 <= ||H00|| + 2 ||H01|| + max |shift| and lambda_min(S) >=
+    lambda_min(S00) - 2 ||S01|| (Weyl's inequality), times `margin`."""
+    norm2 = lambda X: np.linalg.norm(X, 2)
+    h = norm2(layer.H00) + 2 * norm2(layer.H01) + max([abs(v) for v in (shifts or {}).values()] + [0.0])
+    s_min = np.linalg.eigvalsh(layer.S00)[0] - 2 * norm2(layer.S01)
+    if s_min <= 0:
+        raise ValueError("the overlap bound is not positive")
+    e = margin * h / s_min
+    return -e, e
+
+
 def c5_lead(m: int) -> Lead:
     """The lead type of block size m (4 seeded lead types, one per block size)."""
     return decay_layer(500 + m, 0, m)

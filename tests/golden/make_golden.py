@@ -1,14 +1,26 @@
-"""Write the oracle's expected transmissions for sampled energies of the full-size workloads.
+"""Write the oracle's expected values for sampled energies of the full-size workloads.
 
 Calls only ``oracle`` and ``synth`` (no GPU code).  Usage:
-    python tests/golden/make_golden.py c2 c3 c4
-Each output tests/golden/<cfg>.json holds the grid indices, energies and the
-FP64 oracle's T_LR (block-Thomas solve, Sancho-Rubio leads) plus the imaginary
-part of the trace and the decimation iteration counts.
+    python tests/golden/make_golden.py [name ...]
+with names from c2 c3 c4 kmesh_m256 bias_m1024 kpm_m1024 (default: all).
 
-Samples: C2 -- 16 seeded grid points plus the 8 grid points nearest to the
-lead's band extrema (bands on 512 k-points); C3 -- 6 seeded grid points;
-C4 -- 2 seeded grid points (about 3 CPU-minutes each on 8 cores).
+Transmission configs (tests/golden/<cfg>.json): grid indices, energies and
+the FP64 oracle's T_LR (block-Thomas solve, Sancho-Rubio leads), the
+imaginary part of the trace and the decimation iteration counts.
+  c2 -- every one of the 1000 grid energies;
+  c3 -- 120 seeded grid points plus the 8 grid points nearest the lead's band
+        extrema (bands on 512 k-points);
+  c4 -- 8 seeded grid points plus the 8 nearest the band extrema (bands on
+        256 k-points); about 3 CPU-minutes per energy on 8 cores.
+The forms beyond T(E) at the shapes the benchmark times, reduced in the
+layer count only:
+  kmesh_m256 -- the benchmark's k-mesh recipe (decay-weighted layers of
+        M = 256 with transverse images on both in-plane axes) at N = 4 on the
+        7 x 7 mesh, 2 energies: every T_k and the average;
+  bias_m1024 -- the C4 device's first 3 layers at V_b = 0.2 V (electrodes
+        shifted by +-0.1 eV), 3 energies of the bias window;
+  kpm_m1024 -- the C4 central region's first 4 layers (N M = 4096), 4
+        random-phase vectors, 48 Chebyshev moments with the norm bounds.
 """
 from __future__ import annotations
 
@@ -24,51 +36,112 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 import oracle  # noqa: E402
+import oracle.bias as obias  # noqa: E402
+import oracle.kmesh as okm  # noqa: E402
+import oracle.kpm as okpm  # noqa: E402
 import synth  # noqa: E402
 
-SAMPLES = {"c2": (16, 8), "c3": (6, 0), "c4": (2, 0)}
+# (seeded energies, band-edge energies, k-points for the band extrema); None: every grid point
+SAMPLES = {"c2": None, "c3": (120, 8, 512), "c4": (8, 8, 256)}
+
+# the reduced NEXT-row cases (recipe parameters shared with the tests through this module)
+KMESH = {"N": 4, "M": 256, "mesh": 7, "image_seed": 77, "grid": (-1.0, 1.0, 16), "pick": [5, 11]}
+BIAS = {"N": 3, "V": 0.2, "energies": [-0.35, 0.02, 0.31]}
+KPM = {"N": 4, "R": 4, "n_mom": 48, "vector_seed": 2024}
 
 
-def sample_indices(cfg, n_rand: int, n_edge: int, seed: int) -> np.ndarray:
+def sample_indices(cfg, n_rand: int, n_edge: int, nk: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(np.random.SeedSequence([seed, 0, 7]))
     idx = set(rng.choice(len(cfg.energies), size=n_rand, replace=False).tolist())
     if n_edge:
-        ext = oracle.band_extrema(cfg.device.left, nk=512)
+        ext = oracle.band_extrema(cfg.device.left, nk=nk)
         dist = np.min(np.abs(cfg.energies[:, None] - ext[None, :]), axis=1)
-        for i in np.argsort(dist):
+        for i in np.argsort(dist, kind="stable"):
             if len(idx) >= n_rand + n_edge:
                 break
             idx.add(int(i))
     return np.array(sorted(idx))
 
 
+def write(name, out):
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"{name}: {out.get('cpu_seconds')} s -> {path}", flush=True)
+
+
+def transmission_config(name):
+    cfg = {"c2": synth.config_c2, "c3": synth.config_c3, "c4": synth.config_c4}[name]()
+    spec = SAMPLES[name]
+    if spec is None:
+        idx = np.arange(len(cfg.energies))
+    else:
+        idx = sample_indices(cfg, *spec, seed={"c2": 2, "c3": 3, "c4": 4}[name])
+    E = cfg.energies[idx]
+    t0 = time.time()
+    T, tr, infos = oracle.transmission(cfg.device, E, cfg.eta, method="thomas", return_info=True)
+    write(name, {
+        "config": name, "N": cfg.device.N, "M": cfg.device.M, "eta": cfg.eta, "n_grid": len(cfg.energies),
+        "indices": idx.tolist(), "E": E.tolist(), "T": T.tolist(), "imag_trace": tr.imag.tolist(),
+        "sr_iters": [i["iters_left"] for i in infos],
+        "band_edge_samples": 0 if spec is None else spec[1],
+        "oracle": "oracle.transmission(method='thomas'), FP64, Sancho-Rubio leads",
+        "cpu_seconds": round(time.time() - t0, 1)})
+
+
+def kmesh_device():
+    cfg = synth.config_c2(n_layers=KMESH["N"], m=KMESH["M"], n_e=KMESH["grid"][2])
+    images, R = synth.transverse_images(cfg.device, seed=KMESH["image_seed"])
+    kk, w = okm.monkhorst_pack(KMESH["mesh"], KMESH["mesh"])
+    E = np.linspace(*KMESH["grid"])[KMESH["pick"]]
+    return cfg, images, R, kk, w, E
+
+
+def bias_device():
+    cfg = synth.config_c4()
+    d = cfg.device
+    shifts = {k: v for k, v in d.shifts.items() if k < BIAS["N"]}
+    return cfg, synth.Device(BIAS["N"], d.M, d.left, d.right, base=d.base, shifts=shifts, name="c4-first3")
+
+
+def kpm_device():
+    cfg = synth.config_c4(n_e=1)
+    d = cfg.device
+    shifts = {k: v for k, v in d.shifts.items() if k < KPM["N"]}
+    sub = synth.Device(KPM["N"], d.M, d.left, d.right, base=d.base, shifts=shifts, name="c4-first4")
+    lo, hi = synth.kpm_bounds(d.base, d.shifts)
+    r = synth.phase_vectors(KPM["N"] * d.M, KPM["R"], KPM["vector_seed"])
+    return sub, lo, hi, r
+
+
 def main(names):
     for name in names:
-        cfg = {"c2": synth.config_c2, "c3": synth.config_c3, "c4": synth.config_c4}[name]()
-        n_rand, n_edge = SAMPLES[name]
-        idx = sample_indices(cfg, n_rand, n_edge, seed={"c2": 2, "c3": 3, "c4": 4}[name])
-        E = cfg.energies[idx]
         t0 = time.time()
-        T, tr, infos = oracle.transmission(cfg.device, E, cfg.eta, method="thomas", return_info=True)
-        out = {
-            "config": name,
-            "N": cfg.device.N,
-            "M": cfg.device.M,
-            "eta": cfg.eta,
-            "n_grid": len(cfg.energies),
-            "indices": idx.tolist(),
-            "E": E.tolist(),
-            "T": T.tolist(),
-            "imag_trace": tr.imag.tolist(),
-            "sr_iters": [i["iters_left"] for i in infos],
-            "oracle": "oracle.transmission(method='thomas'), FP64, Sancho-Rubio leads",
-            "cpu_seconds": round(time.time() - t0, 1),
-        }
-        path = os.path.join(HERE, f"{name}.json")
-        with open(path, "w") as f:
-            json.dump(out, f, indent=1)
-        print(f"{name}: {len(E)} energies in {out['cpu_seconds']} s -> {path}", flush=True)
+        if name in SAMPLES:
+            transmission_config(name)
+        elif name == "kmesh_m256":
+            cfg, images, R, kk, w, E = kmesh_device()
+            T, Tk = okm.transmission_kmesh(images, R, kk, w, E, cfg.eta, method="thomas")
+            write(name, {**KMESH, "eta": cfg.eta, "E": E.tolist(), "T": T.tolist(), "Tk": Tk.tolist(),
+                         "kpts": kk.tolist(), "weights": w.tolist(), "R": [list(r) for r in R],
+                         "oracle": "oracle.kmesh.transmission_kmesh(method='thomas')",
+                         "cpu_seconds": round(time.time() - t0, 1)})
+        elif name == "bias_m1024":
+            cfg, dev = bias_device()
+            E = np.array(BIAS["energies"])
+            T = obias.transmission_bias(dev, E, cfg.eta, BIAS["V"] / 2, -BIAS["V"] / 2, method="thomas")
+            write(name, {**BIAS, "M": dev.M, "eta": cfg.eta, "E": E.tolist(), "T": T.tolist(),
+                         "oracle": "oracle.bias.transmission_bias(method='thomas')",
+                         "cpu_seconds": round(time.time() - t0, 1)})
+        elif name == "kpm_m1024":
+            dev, lo, hi, r = kpm_device()
+            mu = okpm.moments(dev, lo, hi, KPM["n_mom"], r)
+            write(name, {**KPM, "M": dev.M, "bounds": [lo, hi], "mu": mu.tolist(),
+                         "oracle": "oracle.kpm.moments (dense S solves)",
+                         "cpu_seconds": round(time.time() - t0, 1)})
+        else:
+            raise SystemExit(f"unknown golden {name}")
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["c2", "c3", "c4"])
+    main(sys.argv[1:] or ["kpm_m1024", "bias_m1024", "kmesh_m256", "c2", "c3", "c4"])

@@ -66,6 +66,36 @@ def test_argument_errors_before_device_work(lib):
     assert L.rgf_set_checks(1) == rgf.RGF_OK and L.rgf_get_checks() == 1
     assert L.rgf_set_checks(0) == rgf.RGF_OK and L.rgf_get_checks() == 0
     assert L.rgf_profile(16) == rgf.RGF_OK and L.rgf_profile(0) == rgf.RGF_OK
+    assert L.rgf_profile_classes(1, 1 << 7) == rgf.RGF_EINVAL  # no class 7
+    assert L.rgf_profile_classes(-1, 1) == rgf.RGF_EINVAL
+    assert L.rgf_profile_classes(3, (1 << 7) - 1) == rgf.RGF_OK and L.rgf_profile_classes(0, 0) == rgf.RGF_OK
+    n = C.c_int64()
+    assert L.rgf_profile_read_class(7, C.byref(n), None, None, None, None) == rgf.RGF_EINVAL
+
+
+def test_decimation_cap_setting(lib):
+    """rgf_set_sr_maxit: [1, 100] sets the cap, 0 restores 100, anything else is rejected."""
+    from paper_2609_37058_amd import rgf
+    rgf.load()
+    L = rgf._lib
+    assert L.rgf_get_sr_maxit() == 100
+    assert L.rgf_set_sr_maxit(101) == rgf.RGF_EINVAL and L.rgf_get_sr_maxit() == 100
+    assert L.rgf_set_sr_maxit(-1) == rgf.RGF_EINVAL
+    rgf.set_sr_maxit(3)
+    assert rgf.get_sr_maxit() == 3
+    rgf.set_sr_maxit(0)
+    assert rgf.get_sr_maxit() == 100
+
+
+def test_binding_rejects_wrong_dtypes():
+    """The binding checks what the C calls read and write through each pointer (CPU tensors are
+    refused before any dtype question, so this runs without a GPU)."""
+    import torch
+    from paper_2609_37058_amd import rgf
+    with pytest.raises(ValueError, match="float64"):
+        rgf._energies(torch.zeros(4, dtype=torch.float32))
+    with pytest.raises(ValueError, match="device tensors"):
+        rgf._ptr(torch.zeros(4, dtype=torch.float64), torch.float64, "E")
 
 
 def test_tuning_table_on_the_host(tmp_path):
