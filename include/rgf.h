@@ -265,19 +265,31 @@ int lead_self_energy(const rgf_lead* lead, int side, const double* E, int64_t nE
 /*
  * Serving: a request loop with continuous batching.  transport_submit copies
  * the HOST inputs (device blocks, energies) into library staging before it
- * returns, so the caller may free them at once; the request is admitted to
- * the GPU when the HBM budget and a slot allow; requests in flight overlap on
- * the device.  Lead self-energies (always FP64) are cached on the device per
- * (lead key, side, E bit pattern, eta) under lead_cache_bytes;
- * equal keys MUST mean identical lead blocks.  transport_poll copies T and
- * info to HOST buffers [nE] and the submit-to-completion latency in seconds;
- * it returns RGF_EAGAIN while the request is not finished, and RGF_ENOTICKET
- * once collected.  submit and poll may be called from several threads.
+ * returns, so the caller may free them at once.  Admission: the queue is
+ * scanned in arrival order and every request whose device blocks fit in what
+ * the HBM budget leaves is admitted, so a request that does not fit does not
+ * block smaller ones behind it; once the oldest waiting request has been
+ * passed over 4 times, nothing more is admitted ahead of it until it fits.
+ * An admitted request runs as work items of up to 128 energies (fewer when
+ * the engine workspace of that many does not fit a worker's arena);
+ * max_slots worker threads, each with its own stream and arena, take items
+ * round-robin over the admitted requests, so requests in flight overlap on
+ * the device and a long request never holds a worker for more than one item.
+ * Lead self-energies (always FP64) are cached on the device per (lead key,
+ * side, E bit pattern, eta) under lead_cache_bytes; equal keys MUST mean
+ * identical lead blocks.  transport_poll copies T and info to HOST buffers
+ * [nE] and the submit-to-completion latency in seconds; it returns
+ * RGF_EAGAIN while the request is not finished, and RGF_ENOTICKET once
+ * collected.  submit and poll may be called from several threads.
+ * transport_submit returns RGF_ETOOBIG when one energy's workspace exceeds a
+ * worker's arena or the request's blocks exceed the room the arenas leave.
  * transport_close drains the requests in flight and frees every device
  * buffer of the server.
  */
 typedef struct {
-  uint64_t hbm_budget_bytes; /* device memory for requests in flight (0: 60% of free) */
+  uint64_t hbm_budget_bytes; /* device memory of the server (0: 60% of free): half of it, at most
+                                16 GiB per slot, is the workers' arenas, the rest holds the blocks
+                                of the requests in flight */
   uint64_t lead_cache_bytes; /* device memory for cached lead self-energies */
   int32_t max_slots;         /* requests in flight at once (0: 4) */
 } rgf_server_opts;
@@ -288,9 +300,10 @@ int transport_submit(void* server, const rgf_device* dev, uint64_t lead_key_L, u
 int transport_poll(void* server, uint64_t ticket, double* T, int32_t* info, double* latency_s);
 int transport_close(void* server);
 
-/* Serving counters: requests finished, lead-cache hits and misses, peak bytes in flight. */
+/* Serving counters: requests finished, lead-cache hits and misses (energies), peak device bytes in
+   flight (arenas included), lead-cache bytes, and requests admitted ahead of an older waiting one. */
 typedef struct {
-  uint64_t finished, cache_hits, cache_misses, peak_inflight_bytes, cache_bytes;
+  uint64_t finished, cache_hits, cache_misses, peak_inflight_bytes, cache_bytes, admitted_ahead;
 } rgf_server_stats;
 int transport_stats(void* server, rgf_server_stats* stats);
 

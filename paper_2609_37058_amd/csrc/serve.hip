@@ -2,23 +2,34 @@
 // cache of lead self-energies.
 //
 // transport_submit copies a request's host inputs into library-owned host
-// staging and queues it.  max_slots worker threads each own one HIP stream
-// (default priority); a free worker takes the request at the head of the
-// queue as soon as the memory it needs (device blocks, energies, results
-// and the engine workspace for its energy chunk) fits in what is left of
-// the HBM budget, so requests that arrive while others run are admitted as
-// slots and memory free up, and their kernels overlap on the device.
+// staging and queues it.  A request is ADMITTED when its device blocks fit in
+// what the HBM budget leaves after the requests in flight (the workers'
+// arenas are reserved up front): the queue is scanned in arrival order and
+// every request that fits is admitted, so a large request at the head does
+// not block smaller ones behind it -- but once the head has been passed over
+// AGING_MAX times, nothing more is admitted ahead of it until it fits (no
+// starvation).  An admitted request is split into WORK ITEMS of at most B
+// energies (B sized so one item's engine workspace fits a worker's arena and
+// its work stays bounded), separately for energies whose two self-energies
+// are cached and for the rest.  max_slots worker threads, each with its own
+// HIP stream (default priority) and arena, take items round-robin over the
+// admitted requests: items of one request run on several workers at once,
+// and a long request never holds a worker for longer than one item, so
+// requests that arrive later start as soon as a worker frees up and their
+// kernels overlap on the device with the others'.
+//
+// A request's blocks are copied to the device (stream-ordered allocation) by
+// the worker that takes its first item; the others wait on that copy's
+// event.  The last item to finish frees them.
 //
 // Lead cache: Sigma_L and Sigma_R (padded Mp x Mp, FP64) per
 // (lead key, side, eta, E) in slabs of device memory under
-// lead_cache_bytes, evicted least-recently-used.  A request splits its
-// energies into those with both self-energies cached (decimation skipped,
-// Sigma copied in) and the rest (full path; their Sigma inserted after).
-// An entry written on one stream carries an event that readers on other
-// streams wait on; entries in use by a request are pinned.
+// lead_cache_bytes, evicted least-recently-used.  An entry written on one
+// stream carries an event that readers on other streams wait on; entries in
+// use by a request are pinned.
 //
 // Results for an energy do not depend on the mix: every per-energy step is
-// independent of the other energies in the chunk, and a cached Sigma is the
+// independent of the other energies of a work item, and a cached Sigma is the
 // bitwise value the same FP64 path computed.
 #include <algorithm>
 #include <atomic>
@@ -161,6 +172,17 @@ class LeadCache {
   std::unordered_map<CacheKey, Entry*, CacheKeyHash> map_;
 };
 
+struct Request;
+
+// A work item: energies idx (positions in the request) of one request, with both
+// self-energies cached (`cached`, the pinned entries in `hits`) or computed.
+struct Item {
+  Request* r = nullptr;
+  std::vector<int64_t> idx;
+  bool cached = false;
+  std::vector<std::pair<Entry*, Entry*>> hits;
+};
+
 struct Request {
   uint64_t ticket = 0;
   int N = 0, M = 0;
@@ -174,24 +196,41 @@ struct Request {
   std::vector<double> T;
   std::vector<int32_t> info;
   int chunk = 1;
-  size_t reserve = 0;
+  size_t reserve = 0;  // device bytes while in flight (its blocks)
   double t_submit = 0.0, t_done = 0.0;
-  int state = 0;  // 0 queued, 1 running, 2 done, 3 failed
+  int state = 0;       // 0 queued, 1 admitted, 2 done, 3 failed
   int err = RGF_OK;
   std::string msg;
+  // scheduling (under the server lock)
+  int bypassed = 0;            // times a later request was admitted ahead of this one
+  std::deque<Item> todo;       // items not started
+  int left = 0;                // items not finished
+  int stage = 0;               // 0 not staged, 1 being staged, 2 staged
+  std::vector<Entry*> pinned;  // cache entries pinned for the cached items
+  // device copy of the blocks (valid once stage == 2; readers wait on `staged`)
+  rgf_z* dblocks = nullptr;
+  hipEvent_t staged = nullptr;
+  rgf_device dev{};
 };
 
 size_t block_count(int N, bool same) { return (size_t)2 * N + 2 * (size_t)std::max(N - 1, 0) + (same ? 4 : 8); }
 
 class Server {
  public:
+  static constexpr int AGING_MAX = 4;  // later requests admitted ahead of the head at most this often
+
   Server(const rgf_server_opts& o) : cache_(o.lead_cache_bytes) {
     RGF_HIP(hipGetDevice(&dev_));
     size_t fr = 0, tot = 0;
     RGF_HIP(hipMemGetInfo(&fr, &tot));
     budget_ = o.hbm_budget_bytes ? o.hbm_budget_bytes : (uint64_t)(0.6 * (double)fr);
-    const int slots = o.max_slots > 0 ? o.max_slots : 4;
-    for (int i = 0; i < slots; ++i) workers_.emplace_back([this] { work(); });
+    slots_ = o.max_slots > 0 ? o.max_slots : 4;
+    // every worker's arena is reserved up front: half of the budget over the slots (at most 16 GiB
+    // each, which holds 64 energies at M = 1024)
+    ws_bytes_ = std::min<uint64_t>(budget_ / (2 * (uint64_t)slots_), (uint64_t)16 << 30);
+    inflight_ = ws_bytes_ * slots_;
+    peak_ = inflight_;
+    for (int i = 0; i < slots_; ++i) workers_.emplace_back([this] { work(); });
   }
   ~Server() {
     {
@@ -201,6 +240,11 @@ class Server {
     cv_work_.notify_all();
     for (auto& t : workers_) t.join();
   }
+
+  uint64_t budget() const { return budget_; }
+  uint64_t ws_bytes() const { return ws_bytes_; }
+  // room for the blocks of requests in flight
+  uint64_t block_budget() const { return budget_ > ws_bytes_ * slots_ ? budget_ - ws_bytes_ * slots_ : 0; }
 
   uint64_t submit(std::unique_ptr<Request> r) {
     std::lock_guard<std::mutex> lk(mu_);
@@ -229,11 +273,11 @@ class Server {
     all_.erase(it);
     return RGF_OK;
   }
-  uint64_t budget() const { return budget_; }
   void stats(rgf_server_stats* s) {
     std::lock_guard<std::mutex> lk(mu_);
     s->finished = finished_;
     s->peak_inflight_bytes = peak_;
+    s->admitted_ahead = ahead_;
     std::lock_guard<std::mutex> lc(cache_.mu);
     s->cache_hits = cache_.hits;
     s->cache_misses = cache_.misses;
@@ -242,89 +286,130 @@ class Server {
 
  private:
   void work();
-  void process(Request* r, hipStream_t st, int32_t* host_active);
+  void admit_locked();
+  Item* pick_locked(Request** owner);
+  void stage_blocks(Request* r, hipStream_t st);
+  void run_item(Item& it, char* ws, hipStream_t st, int32_t* host_active, std::vector<double>& hT,
+                std::vector<int32_t>& hI);
+  void finish_item_locked(Request* r, bool failed, const Error& e, hipStream_t st);
 
-  int dev_ = 0;
-  uint64_t budget_ = 0;
+  int dev_ = 0, slots_ = 4;
+  uint64_t budget_ = 0, ws_bytes_ = 0;
   std::mutex mu_;
   std::condition_variable cv_work_;
-  std::deque<Request*> queue_;
+  std::deque<Request*> queue_;   // submitted, not admitted (arrival order)
+  std::vector<Request*> active_;  // admitted with items not yet started
+  size_t rr_ = 0;                 // round-robin cursor over active_
   std::map<uint64_t, std::unique_ptr<Request>> all_;
-  uint64_t next_ = 0, inflight_ = 0, peak_ = 0, finished_ = 0;
+  uint64_t next_ = 0, inflight_ = 0, peak_ = 0, finished_ = 0, ahead_ = 0;
+  int running_ = 0;  // items being run
   bool stop_ = false;
   std::vector<std::thread> workers_;
   LeadCache cache_;
 };
 
-void Server::work() {
-  (void)hipSetDevice(dev_);
-  hipStream_t st = nullptr;
-  int32_t* host_active = nullptr;
-  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-      hipHostMalloc((void**)&host_active, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
-    return;
-  }
-  for (;;) {
-    Request* r = nullptr;
+// Admit queued requests in arrival order while their blocks fit; the head may be passed over
+// at most AGING_MAX times.  Each admitted request gets its work items (cache lookup and pins).
+void Server::admit_locked() {
+  const uint64_t room = block_budget();
+  const uint64_t used = inflight_ - ws_bytes_ * slots_;
+  uint64_t free_b = room > used ? room - used : 0;
+  for (auto it = queue_.begin(); it != queue_.end();) {
+    Request* r = *it;
+    const bool head = it == queue_.begin();
+    if (r->reserve > free_b) {
+      if (head && r->bypassed >= AGING_MAX) return;  // the head waits for room
+      ++it;
+      continue;
+    }
+    if (!head) {  // admitted ahead of the waiting head: at most AGING_MAX times per head
+      Request* h = queue_.front();
+      if (h->bypassed >= AGING_MAX) return;
+      h->bypassed++;
+      ++ahead_;
+    }
+    free_b -= r->reserve;
+    inflight_ += r->reserve;
+    peak_ = std::max(peak_, inflight_);
+    r->state = 1;
+    // work items: cached energies (both sides, this block size) and the rest, B at a time
+    const int Mp = (int)round_up(r->M, 64);
+    uint64_t eta_bits;
+    std::memcpy(&eta_bits, &r->eta, 8);
+    std::vector<int64_t> miss;
+    std::vector<std::pair<int64_t, std::pair<Entry*, Entry*>>> hit;
     {
-      std::unique_lock<std::mutex> lk(mu_);
-      cv_work_.wait(lk, [&] {
-        return (stop_ && queue_.empty()) || (!queue_.empty() && inflight_ + queue_.front()->reserve <= budget_);
-      });
-      if (queue_.empty()) break;
-      r = queue_.front();
-      queue_.pop_front();
-      inflight_ += r->reserve;
-      peak_ = std::max(peak_, inflight_);
-      r->state = 1;
+      std::lock_guard<std::mutex> lc(cache_.mu);
+      for (int64_t k = 0; k < r->nE; ++k) {
+        uint64_t eb;
+        std::memcpy(&eb, &r->E[k], 8);
+        Entry* el = cache_.find({r->keyL, eta_bits, eb, RGF_LEFT});
+        Entry* er = cache_.find({r->keyR, eta_bits, eb, RGF_RIGHT});
+        if (el && er && el->mp == Mp && er->mp == Mp) {
+          el->pins++;
+          er->pins++;
+          r->pinned.push_back(el);
+          r->pinned.push_back(er);
+          hit.push_back({k, {el, er}});
+          cache_.hits++;
+        } else {
+          miss.push_back(k);
+          cache_.misses++;
+        }
+      }
     }
-    int state = 2, err = RGF_OK;
-    std::string msg;
-    try {
-      process(r, st, host_active);
-    } catch (const Error& e) {
-      state = 3;
-      err = e.code;
-      msg = e.msg;
-      (void)hipStreamSynchronize(st);
+    for (size_t c = 0; c < miss.size(); c += r->chunk) {
+      Item w;
+      w.r = r;
+      w.idx.assign(miss.begin() + c, miss.begin() + std::min(miss.size(), c + r->chunk));
+      r->todo.push_back(std::move(w));
     }
-    {
-      std::lock_guard<std::mutex> lk(mu_);
-      r->t_done = now_s();
-      r->err = err;
-      r->msg = msg;
-      r->state = state;
-      inflight_ -= r->reserve;
-      ++finished_;
+    for (size_t c = 0; c < hit.size(); c += r->chunk) {
+      Item w;
+      w.r = r;
+      w.cached = true;
+      for (size_t j = c; j < std::min(hit.size(), c + r->chunk); ++j) {
+        w.idx.push_back(hit[j].first);
+        w.hits.push_back(hit[j].second);
+      }
+      r->todo.push_back(std::move(w));
     }
-    cv_work_.notify_all();
+    r->left = (int)r->todo.size();
+    active_.push_back(r);
+    it = queue_.erase(it);
   }
-  (void)hipStreamDestroy(st);
-  (void)hipHostFree(host_active);
 }
 
-struct DevBuf {
-  void* p = nullptr;
-  explicit DevBuf(size_t n) {
-    if (n && hipMalloc(&p, n) != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error{RGF_ENOMEM, "serving: device allocation failed"};
-    }
+// The next item, round-robin over the admitted requests; a request being staged by another
+// worker is skipped until its copy is enqueued.  Returns nullptr when nothing can start.
+Item* Server::pick_locked(Request** owner) {
+  const size_t n = active_.size();
+  for (size_t k = 0; k < n; ++k) {
+    const size_t i = (rr_ + k) % n;
+    Request* r = active_[i];
+    if (r->todo.empty() || r->stage == 1) continue;
+    rr_ = (i + 1) % std::max<size_t>(1, n);
+    *owner = r;
+    return &r->todo.front();
   }
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
-};
+  return nullptr;
+}
 
-void Server::process(Request* r, hipStream_t st, int32_t* host_active) {
+void Server::stage_blocks(Request* r, hipStream_t st) {
+  const size_t MMu = (size_t)r->M * r->M;
+  const size_t bytes = block_count(r->N, r->same_leads) * MMu * sizeof(rgf_z);
+  void* p = nullptr;
+  if (hipMallocAsync(&p, bytes, st) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{RGF_ENOMEM, "serving: device allocation of the request's blocks failed"};
+  }
+  r->dblocks = static_cast<rgf_z*>(p);
+  RGF_HIP(hipMemcpyAsync(p, r->blocks.data(), bytes, hipMemcpyHostToDevice, st));
+  RGF_HIP(hipEventCreateWithFlags(&r->staged, hipEventDisableTiming));
+  RGF_HIP(hipEventRecord(r->staged, st));
   const int N = r->N, M = r->M;
-  const int Mp = (int)round_up(M, 64);
-  const size_t MMu = (size_t)M * M;
-  const size_t nb = block_count(N, r->same_leads);
-  DevBuf blocks(nb * MMu * sizeof(rgf_z));
-  RGF_HIP(hipMemcpyAsync(blocks.p, r->blocks.data(), nb * MMu * sizeof(rgf_z), hipMemcpyHostToDevice, st));
-  rgf_z* b0 = static_cast<rgf_z*>(blocks.p);
-  rgf_device d;
+  rgf_z* b0 = r->dblocks;
+  rgf_device& d = r->dev;
   d.N = N;
   d.M = M;
   d.Hd = b0;
@@ -334,122 +419,177 @@ void Server::process(Request* r, hipStream_t st, int32_t* host_active) {
   rgf_z* lp = b0 + (2 * N + 2 * std::max(N - 1, 0)) * MMu;
   d.left = rgf_lead{M, lp, lp + MMu, lp + 2 * MMu, lp + 3 * MMu};
   d.right = r->same_leads ? d.left : rgf_lead{M, lp + 4 * MMu, lp + 5 * MMu, lp + 6 * MMu, lp + 7 * MMu};
-
-  const int B = r->chunk;
-  const Layout lay = Layout::make(Mp, B);
-  DevBuf ws(lay.bytes);
-  DevBuf dE(sizeof(double) * B);
-  DevBuf dT(sizeof(double) * B);
-  DevBuf dI(sizeof(int32_t) * B);
-  std::vector<double> hE(B);
-  std::vector<double> hT(B);
-  std::vector<int32_t> hI(B);
-
-  // split the energies into cache hits (both sides cached) and misses
-  const uint64_t eta_bits = [&] {
-    uint64_t v;
-    std::memcpy(&v, &r->eta, 8);
-    return v;
-  }();
-  std::vector<int64_t> hit_idx, miss_idx;
-  std::vector<Entry*> pinned;
-  std::vector<std::pair<Entry*, Entry*>> hit_entries;
-  {
-    std::lock_guard<std::mutex> lk(cache_.mu);
-    for (int64_t k = 0; k < r->nE; ++k) {
-      uint64_t eb;
-      std::memcpy(&eb, &r->E[k], 8);
-      Entry* el = cache_.find({r->keyL, eta_bits, eb, RGF_LEFT});
-      Entry* er = cache_.find({r->keyR, eta_bits, eb, RGF_RIGHT});
-      if (el && er && el->mp == Mp && er->mp == Mp) {
-        el->pins++;
-        er->pins++;
-        pinned.push_back(el);
-        pinned.push_back(er);
-        hit_idx.push_back(k);
-        hit_entries.push_back({el, er});
-        cache_.hits++;
-      } else {
-        miss_idx.push_back(k);
-        cache_.misses++;
-      }
-    }
-  }
-  auto unpin = [&] {
-    std::lock_guard<std::mutex> lk(cache_.mu);
-    for (Entry* e : pinned) e->pins--;
-    pinned.clear();
-  };
-  try {
-    auto run = [&](const std::vector<int64_t>& idx, bool cached) {
-      for (size_t c0 = 0; c0 < idx.size(); c0 += B) {
-        const int nb_ = (int)std::min<size_t>(B, idx.size() - c0);
-        for (int j = 0; j < nb_; ++j) hE[j] = r->E[idx[c0 + j]];
-        RGF_HIP(hipMemcpyAsync(dE.p, hE.data(), sizeof(double) * nb_, hipMemcpyHostToDevice, st));
-        Layout l2 = Layout::make(Mp, nb_);
-        Engine eng(static_cast<char*>(ws.p), l2, st, r->prec == RGF_MIXED ? PREC_F32 : PREC_F64, M,
-                   static_cast<double*>(dE.p), r->eta, host_active);
-        if (cached) {
-          for (int j = 0; j < nb_; ++j) {
-            auto pr = hit_entries[c0 + j];
-            RGF_HIP(hipStreamWaitEvent(st, pr.first->ready, 0));
-            RGF_HIP(hipStreamWaitEvent(st, pr.second->ready, 0));
-            RGF_HIP(hipMemcpyAsync(eng.sigma_slot(j, true), pr.first->ptr, sizeof(z64) * eng.block_elems(),
-                                   hipMemcpyDeviceToDevice, st));
-            RGF_HIP(hipMemcpyAsync(eng.sigma_slot(j, false), pr.second->ptr, sizeof(z64) * eng.block_elems(),
-                                   hipMemcpyDeviceToDevice, st));
-          }
-          RGF_HIP(hipMemsetAsync(eng.done_l(), 0xFF, sizeof(int32_t) * 2 * nb_, st));  // decimation not run
-        } else {
-          eng.decimate(d.left, eng.done_l());
-          eng.self_energy(d.left, true, eng.sigL());
-          if (!r->same_leads) eng.decimate(d.right, eng.done_r());
-          eng.self_energy(d.right, false, eng.sigR());
-        }
-        eng.broadenings();
-        eng.sweep_and_trace(d, static_cast<double*>(dT.p), static_cast<int32_t*>(dI.p), r->same_leads);
-        if (!cached) {
-          // insert the new self-energies (only fully converged ones)
-          RGF_HIP(hipMemcpyAsync(hI.data(), dI.p, sizeof(int32_t) * nb_, hipMemcpyDeviceToHost, st));
-          RGF_HIP(hipStreamSynchronize(st));
-          std::lock_guard<std::mutex> lk(cache_.mu);
-          for (int j = 0; j < nb_; ++j) {
-            if (hI[j] != 0) continue;
-            uint64_t eb;
-            std::memcpy(&eb, &hE[j], 8);
-            for (int side = 0; side < 2; ++side) {
-              const CacheKey key{side == 0 ? r->keyL : r->keyR, eta_bits, eb, side};
-              if (cache_.find(key)) continue;
-              Entry* e = cache_.insert(key, Mp);
-              if (!e) continue;
-              RGF_HIP(hipMemcpyAsync(e->ptr, eng.sigma_slot(j, side == 0), sizeof(z64) * eng.block_elems(),
-                                     hipMemcpyDeviceToDevice, st));
-              RGF_HIP(hipEventRecord(e->ready, st));
-            }
-          }
-        }
-        RGF_HIP(hipMemcpyAsync(hT.data(), dT.p, sizeof(double) * nb_, hipMemcpyDeviceToHost, st));
-        RGF_HIP(hipMemcpyAsync(hI.data(), dI.p, sizeof(int32_t) * nb_, hipMemcpyDeviceToHost, st));
-        RGF_HIP(hipStreamSynchronize(st));
-        for (int j = 0; j < nb_; ++j) {
-          r->T[idx[c0 + j]] = hT[j];
-          r->info[idx[c0 + j]] = hI[j];
-        }
-      }
-    };
-    run(miss_idx, false);
-    run(hit_idx, true);
-  } catch (...) {
-    unpin();
-    throw;
-  }
-  unpin();
 }
 
-// Bytes one request needs on the device at once, for an energy chunk of B.
-size_t request_bytes(int N, int M, bool same, int B) {
-  const size_t Mp = (size_t)round_up(M, 64);
-  return block_count(N, same) * (size_t)M * M * sizeof(rgf_z) + Layout::make((int)Mp, B).bytes + 24 * (size_t)B;
+// One work item on this worker's stream and arena (the chunk's Layout plus its staged
+// energies and outputs); results land in the request's host arrays.
+void Server::run_item(Item& it, char* ws, hipStream_t st, int32_t* host_active, std::vector<double>& hT,
+                      std::vector<int32_t>& hI) {
+  Request* r = it.r;
+  const int M = r->M, Mp = (int)round_up(M, 64);
+  const int nb = (int)it.idx.size();
+  const Layout lay = Layout::make(Mp, nb);
+  double* dE = reinterpret_cast<double*>(ws + lay.energies);
+  double* dT = reinterpret_cast<double*>(ws + lay.tout);
+  int32_t* dI = reinterpret_cast<int32_t*>(ws + lay.iout);
+  hT.resize(nb);
+  hI.resize(nb);
+  std::vector<double> hE(nb);
+  for (int j = 0; j < nb; ++j) hE[j] = r->E[it.idx[j]];
+  RGF_HIP(hipStreamWaitEvent(st, r->staged, 0));
+  RGF_HIP(hipMemcpyAsync(dE, hE.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
+  Engine eng(ws, lay, st, r->prec == RGF_MIXED ? PREC_F32 : PREC_F64, M, dE, r->eta, host_active);
+  const rgf_device& d = r->dev;
+  if (it.cached) {
+    for (int j = 0; j < nb; ++j) {
+      const auto& pr = it.hits[j];
+      RGF_HIP(hipStreamWaitEvent(st, pr.first->ready, 0));
+      RGF_HIP(hipStreamWaitEvent(st, pr.second->ready, 0));
+      RGF_HIP(hipMemcpyAsync(eng.sigma_slot(j, true), pr.first->ptr, sizeof(z64) * eng.block_elems(),
+                             hipMemcpyDeviceToDevice, st));
+      RGF_HIP(hipMemcpyAsync(eng.sigma_slot(j, false), pr.second->ptr, sizeof(z64) * eng.block_elems(),
+                             hipMemcpyDeviceToDevice, st));
+    }
+    RGF_HIP(hipMemsetAsync(eng.done_l(), 0xFF, sizeof(int32_t) * 2 * nb, st));  // decimation not run
+  } else {
+    eng.decimate(d.left, eng.done_l());
+    eng.self_energy(d.left, true, eng.sigL());
+    if (!r->same_leads) eng.decimate(d.right, eng.done_r());
+    eng.self_energy(d.right, false, eng.sigR());
+  }
+  eng.broadenings();
+  eng.sweep_and_trace(d, dT, dI, r->same_leads);
+  RGF_HIP(hipMemcpyAsync(hT.data(), dT, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+  RGF_HIP(hipMemcpyAsync(hI.data(), dI, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
+  RGF_HIP(hipStreamSynchronize(st));
+  if (!it.cached) {  // insert the new self-energies (fully converged energies only)
+    uint64_t eta_bits;
+    std::memcpy(&eta_bits, &r->eta, 8);
+    std::lock_guard<std::mutex> lk(cache_.mu);
+    for (int j = 0; j < nb; ++j) {
+      if (hI[j] != 0) continue;
+      uint64_t eb;
+      std::memcpy(&eb, &hE[j], 8);
+      for (int side = 0; side < 2; ++side) {
+        const CacheKey key{side == 0 ? r->keyL : r->keyR, eta_bits, eb, side};
+        if (cache_.find(key)) continue;
+        Entry* e = cache_.insert(key, Mp);
+        if (!e) continue;
+        RGF_HIP(hipMemcpyAsync(e->ptr, eng.sigma_slot(j, side == 0), sizeof(z64) * eng.block_elems(),
+                               hipMemcpyDeviceToDevice, st));
+        RGF_HIP(hipEventRecord(e->ready, st));
+      }
+    }
+    // the copies out of the arena precede, on this stream, the next item that reuses it
+  }
+}
+
+// Book-keeping after an item (the worker has synchronised its stream): the last item of a
+// request frees its blocks, unpins its cache entries and completes it.
+void Server::finish_item_locked(Request* r, bool failed, const Error& e, hipStream_t st) {
+  --running_;
+  if (failed && r->state != 3) {
+    r->state = 3;
+    r->err = e.code;
+    r->msg = e.msg;
+    r->left -= (int)r->todo.size();  // items not started are dropped
+    r->todo.clear();
+  }
+  if (--r->left > 0) return;
+  if (r->dblocks) (void)hipFreeAsync(r->dblocks, st);
+  r->dblocks = nullptr;
+  if (r->staged) (void)hipEventDestroy(r->staged);
+  r->staged = nullptr;
+  {
+    std::lock_guard<std::mutex> lc(cache_.mu);
+    for (Entry* en : r->pinned) en->pins--;
+    r->pinned.clear();
+  }
+  active_.erase(std::remove(active_.begin(), active_.end(), r), active_.end());
+  inflight_ -= r->reserve;
+  r->t_done = now_s();
+  if (r->state != 3) r->state = 2;
+  r->blocks.clear();
+  r->blocks.shrink_to_fit();
+  ++finished_;
+}
+
+void Server::work() {
+  (void)hipSetDevice(dev_);
+  hipStream_t st = nullptr;
+  int32_t* host_active = nullptr;
+  char* ws = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+      hipHostMalloc((void**)&host_active, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    return;
+  }
+  std::vector<double> hT;
+  std::vector<int32_t> hI;
+  for (;;) {
+    Item it;
+    Request* r = nullptr;
+    bool do_stage = false;
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      Item* p = nullptr;
+      cv_work_.wait(lk, [&] {
+        admit_locked();
+        p = pick_locked(&r);
+        return p != nullptr || (stop_ && queue_.empty() && active_.empty());
+      });
+      if (!p) break;
+      it = std::move(*p);
+      r->todo.pop_front();
+      do_stage = r->stage == 0;
+      if (do_stage) r->stage = 1;
+      ++running_;
+    }
+    bool failed = false;
+    Error err{RGF_OK, ""};
+    try {
+      if (!ws) {
+        if (hipMalloc((void**)&ws, ws_bytes_) != hipSuccess) {
+          (void)hipGetLastError();
+          ws = nullptr;
+          throw Error{RGF_ENOMEM, "serving: worker arena allocation failed"};
+        }
+      }
+      if (do_stage) {
+        stage_blocks(r, st);
+        std::lock_guard<std::mutex> lk(mu_);
+        r->stage = 2;
+        cv_work_.notify_all();  // its other items may start now
+      }
+      run_item(it, ws, st, host_active, hT, hI);
+      std::lock_guard<std::mutex> lk(mu_);
+      for (size_t j = 0; j < it.idx.size(); ++j) {
+        r->T[it.idx[j]] = hT[j];
+        r->info[it.idx[j]] = hI[j];
+      }
+    } catch (const Error& e) {
+      failed = true;
+      err = e;
+      (void)hipStreamSynchronize(st);
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (failed && do_stage && r->stage == 1) r->stage = 2;  // let the remaining items drop out
+      finish_item_locked(r, failed, err, st);
+    }
+    cv_work_.notify_all();
+  }
+  (void)hipStreamSynchronize(st);
+  if (ws) (void)hipFree(ws);
+  (void)hipStreamDestroy(st);
+  (void)hipHostFree(host_active);
+}
+
+// Work-item size: the largest B (at most 128) whose engine workspace fits a worker's arena.
+int item_energies(int M, int64_t nE, uint64_t ws_bytes) {
+  const int Mp = (int)round_up(M, 64);
+  int B = (int)std::min<int64_t>(nE, 128);
+  while (B > 0 && Layout::make(Mp, B).bytes > ws_bytes) B = B > 8 ? B * 3 / 4 : B - 1;
+  return B;
 }
 
 }  // namespace
@@ -532,12 +672,13 @@ int transport_submit(void* server, const rgf_device* dev, uint64_t lead_key_L, u
     r->E.assign(E, E + nE);
     r->T.assign(nE, 0.0);
     r->info.assign(nE, 0);
-    // largest energy chunk whose footprint leaves room for at least one more request
-    int B = (int)std::min<int64_t>(nE, 1024);
-    while (B > 1 && request_bytes(N, dev->M, r->same_leads, B) > s->budget() / 2) B = (B + 1) / 2;
-    const size_t need = request_bytes(N, dev->M, r->same_leads, B);
-    RGF_CHECK(need <= s->budget(), RGF_ETOOBIG, "request needs " + std::to_string(need) +
-                                                    " bytes, more than the whole HBM budget");
+    // work items of B energies fit a worker's arena; the blocks must fit what the arenas leave
+    const int B = item_energies(dev->M, nE, s->ws_bytes());
+    const size_t need = block_count(N, r->same_leads) * MMu * sizeof(rgf_z);
+    RGF_CHECK(B >= 1, RGF_ETOOBIG, "one energy's workspace at M = " + std::to_string(dev->M) +
+                                       " exceeds a worker's share of the HBM budget");
+    RGF_CHECK(need <= s->block_budget(), RGF_ETOOBIG,
+              "request needs " + std::to_string(need) + " bytes of blocks, more than the HBM budget leaves");
     r->chunk = B;
     r->reserve = need;
     *ticket = s->submit(std::move(r));

@@ -46,7 +46,7 @@ class rgf_server_opts(C.Structure):
 
 class rgf_server_stats(C.Structure):
     _fields_ = [("finished", C.c_uint64), ("cache_hits", C.c_uint64), ("cache_misses", C.c_uint64),
-                ("peak_inflight_bytes", C.c_uint64), ("cache_bytes", C.c_uint64)]
+                ("peak_inflight_bytes", C.c_uint64), ("cache_bytes", C.c_uint64), ("admitted_ahead", C.c_uint64)]
 
 
 _lib = None

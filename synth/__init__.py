@@ -298,12 +298,15 @@ def c5_lead(m: int) -> Lead:
 
 
 def c5_requests(n_req: int = 128, qps: float = 1.0, sizes=C5_BLOCK_SIZES, n_layers=(20, 400),
-                n_e=(64, 1024), seed: int = 5) -> List[Request]:
+                n_e=(64, 1024), seed: int = 5, repeated: bool = False) -> List[Request]:
     """Serving mix: Poisson arrivals; M from ``sizes``, N ~ U[20, 400], nE ~ U[64, 1024].
 
     Request r draws its device from seed 5000 + r (decay-layer recipe per
     layer) and its energies as a sorted seeded subset of the common
-    1024-point grid on [-2, 2]; lead type = block-size class.
+    1024-point grid on [-2, 2]; lead type = block-size class.  With
+    ``repeated`` the device is instead layer 0 of that recipe repeated N
+    times with 5% seeded dopant shifts (the C3/C4 recipe): the same shapes
+    and work, without drawing N random layers on the host.
     """
     rng = np.random.default_rng(np.random.SeedSequence([seed, 0, 0]))
     gaps = rng.exponential(1.0 / qps, size=n_req)
@@ -316,10 +319,15 @@ def c5_requests(n_req: int = 128, qps: float = 1.0, sizes=C5_BLOCK_SIZES, n_laye
         ne = int(rr.integers(n_e[0], min(n_e[1], len(C5_GRID)) + 1))
         idx = np.sort(rr.choice(len(C5_GRID), size=ne, replace=False))
         lead = c5_lead(m)
-        layers = [decay_layer(5000 + r, i, m) for i in range(N)]
-        dev = device_from_blocks([l.H00 for l in layers], [l.H01 for l in layers[:-1]],
-                                 [l.S00 for l in layers], [l.S01 for l in layers[:-1]],
-                                 lead, lead, name=f"c5-r{r}")
+        if repeated:
+            base = decay_layer(5000 + r, 0, m)
+            shifts = dopant_shifts(5000 + r, N) if N > 2 else {}
+            dev = Device(N, m, lead, lead, base=base, shifts=shifts, name=f"c5-r{r}")
+        else:
+            layers = [decay_layer(5000 + r, i, m) for i in range(N)]
+            dev = device_from_blocks([l.H00 for l in layers], [l.H01 for l in layers[:-1]],
+                                     [l.S00 for l in layers], [l.S01 for l in layers[:-1]],
+                                     lead, lead, name=f"c5-r{r}")
         out.append(Request(r, float(arrivals[r]), dev, C5_GRID[idx].copy(), lead_key=m))
     return out
 
