@@ -117,6 +117,30 @@ enum {
 int rgf_transmission(const rgf_device* dev, const double* E, int64_t nE, double eta,
                      int precision, double* T, int32_t* info, void* stream);
 
+/*
+ * rgf_transmission_noalloc -- rgf_transmission for callers that cannot
+ * allocate device memory: code in tight serving loops, harnesses that forbid
+ * hipMalloc, or callers that set up all memory in advance.  It computes the
+ * same T(E) with the same kernels (bitwise the values rgf_transmission
+ * returns: every per-energy step is independent of how energies are
+ * chunked), but it calls no hipMalloc, hipFree or other allocating routine:
+ * its workspace is a file-scope device array of RGF_NOALLOC_SCRATCH_BYTES
+ * (128 MiB) that each GPU the library runs on holds from module load until
+ * the process ends.  The energies run in chunks that fit that array, on the
+ * caller's stream only (one lane, no captured graphs, no debug input checks).
+ * Blocks with M <= 16 (FP64) take the small-block kernel, which needs no
+ * scratch memory at all.  RGF_ETOOBIG when one energy's workspace does not fit
+ * the array (M above 704).  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (on different streams or from different
+ * threads) race, so serialise them.  The array keeps the last call's
+ * contents; every flag and counter the path reads is cleared by the call
+ * before use.  The call synchronises its stream during decimation (as
+ * rgf_transmission does), so it cannot be captured into a graph.  Pointers,
+ * precision, info and the other errors as rgf_transmission.
+ */
+#define RGF_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int rgf_transmission_noalloc(const rgf_device* dev, const double* E, int64_t nE, double eta, int precision,
+                             double* T, int32_t* info, void* stream);
 
 /*
  * rgf_transmission_batch -- the batching form: many devices of uneven block

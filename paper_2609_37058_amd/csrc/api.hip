@@ -530,6 +530,62 @@ static void run_range(const rgf_device& d, const double* E, int64_t lo, int64_t 
   }
 }
 
+// ------------------------------------------------ allocation-free variant
+// The arena of rgf_transmission_noalloc: a file-scope device array (each GPU
+// holds its own copy from module load until the process ends).  Host code
+// never passes the array's name to a kernel: the host-side name is a shadow,
+// not a device address.  The device address is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[RGF_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[64] = {};
+static int32_t g_scratch_active[64];  // the decimation's still-active count, read back by the host
+
+static char* scratch_arena(int dev) {
+  RGF_CHECK(dev >= 0 && dev < 64, RGF_EDEVICE, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    RGF_CHECK(e == hipSuccess && p, RGF_EDEVICE,
+              std::string("scratch array address lookup failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Largest energy chunk whose layout fits the scratch array (0: not even one energy).
+static int noalloc_chunk(int Mp, int64_t nE) {
+  const size_t per = Layout::make(Mp, 1).bytes;
+  int64_t b = std::min<int64_t>(nE, (int64_t)(RGF_NOALLOC_SCRATCH_BYTES / per));
+  while (b > 0 && Layout::make(Mp, (int)b).bytes > RGF_NOALLOC_SCRATCH_BYTES) --b;
+  return (int)b;
+}
+
+static void transmission_noalloc_impl(const rgf_device& d, const double* E, int64_t nE, double eta, int precision,
+                                      double* T, int32_t* info, hipStream_t st) {
+  if (uses_small_path(d.M, precision)) {  // every block in LDS: no scratch memory at all
+    launch_small(small_args(d, E, nE, eta, T, info), st);
+    return;
+  }
+  const int Mp = (int)round_up(d.M, 64);
+  const int chunk = noalloc_chunk(Mp, nE);
+  RGF_CHECK(chunk >= 1, RGF_ETOOBIG,
+            "rgf_transmission_noalloc: one energy at M = " + std::to_string(d.M) + " needs " +
+                std::to_string(Layout::make(Mp, 1).bytes) + " bytes, more than the " +
+                std::to_string((size_t)RGF_NOALLOC_SCRATCH_BYTES) + "-byte scratch array");
+  int dev = 0;
+  RGF_HIP(hipGetDevice(&dev));
+  char* base = scratch_arena(dev);
+  std::lock_guard<std::mutex> call(stream_call_mutex(dev, st));
+  for (int64_t e0 = 0; e0 < nE;) {
+    const int B = (int)std::min<int64_t>(chunk, nE - e0);
+    run_chunk(d, E, e0, B, eta, precision, T, info, base, Layout::make(Mp, B), &g_scratch_active[dev], false, st,
+              0.0, 0.0, Grouping());
+    e0 += B;
+  }
+}
+
 void run_device(const rgf_device& d, const double* E, int64_t nE, double eta, int precision, double* T,
                 int32_t* info, hipStream_t st, double mem_share, double u_l, double u_r, const Grouping& grp) {
   if (nE <= 0) return;
@@ -845,6 +901,17 @@ int rgf_transmission(const rgf_device* dev, const double* E, int64_t nE, double 
     if (g_checks) check_inputs(*dev, INPUT_CHECK_TOL, true, (hipStream_t)stream);
     if (nE == 0) return;
     transmission_impl(*dev, E, nE, eta, precision, T, info, (hipStream_t)stream);
+  });
+}
+
+int rgf_transmission_noalloc(const rgf_device* dev, const double* E, int64_t nE, double eta, int precision,
+                             double* T, int32_t* info, void* stream) {
+  return guarded([&] {
+    RGF_CHECK(dev, RGF_EINVAL, "null device");
+    check_device(*dev);
+    check_common(E, nE, eta, precision, T);
+    if (nE == 0) return;
+    transmission_noalloc_impl(*dev, E, nE, eta, precision, T, info, (hipStream_t)stream);
   });
 }
 

@@ -72,6 +72,8 @@ SIGNATURES = {
     "rgf_get_checks": (C.c_int, []),
     "rgf_profile_read": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rgf_profile_classes": (C.c_int, [C.c_int, C.c_uint32]),
+    "rgf_transmission_noalloc": (C.c_int, [C.POINTER(rgf_device), C.c_void_p, C.c_int64, C.c_double, C.c_int,
+                                           C.c_void_p, C.c_void_p, C.c_void_p]),
     "rgf_set_sr_maxit": (C.c_int, [C.c_int32]),
     "rgf_get_sr_maxit": (C.c_int, []),
     "rgf_profile_read_class": (C.c_int, [C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
@@ -228,6 +230,25 @@ def transmission(dev: DeviceTensors, E: torch.Tensor, eta: float, precision="fp6
     d = dev.cstruct()
     _check(lib.rgf_transmission(C.byref(d), _ptr(E, _F64, "E"), nE, float(eta), PRECISION[precision],
                                 _ptr(out, _F64, "out"), _ptr(info, _I32, "info"), _stream(stream)))
+    return out, info
+
+
+#: bytes of the device scratch array behind transmission_noalloc (RGF_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def transmission_noalloc(dev: DeviceTensors, E: torch.Tensor, eta: float, out: torch.Tensor,
+                         info: torch.Tensor, precision="fp64", stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """T(E) into the caller's out (float64) and info (int32) through rgf_transmission_noalloc: the
+    library's workspace is its static device scratch array, so the call allocates nothing."""
+    lib = load()
+    E = _energies(E)
+    nE = E.numel()
+    if out.numel() < nE or info.numel() < nE:
+        raise ValueError("out and info need one element per energy")
+    d = dev.cstruct()
+    _check(lib.rgf_transmission_noalloc(C.byref(d), _ptr(E, _F64, "E"), nE, float(eta), PRECISION[precision],
+                                        _ptr(out, _F64, "out"), _ptr(info, _I32, "info"), _stream(stream)))
     return out, info
 
 

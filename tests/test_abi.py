@@ -87,6 +87,22 @@ def test_decimation_cap_setting(lib):
     assert rgf.get_sr_maxit() == 100
 
 
+def test_noalloc_rejects_blocks_beyond_its_scratch(lib):
+    """A block size whose one-energy workspace exceeds the static scratch array is refused with
+    RGF_ETOOBIG before any device work (the pointers below are never dereferenced)."""
+    from paper_2609_37058_amd import rgf
+    rgf.load()
+    L = rgf._lib
+    fake = 256  # non-null, never read: the size check comes first
+    for M, ok in ((768, False), (2048, False)):
+        lead = rgf.rgf_lead(M, fake, fake, fake, fake)
+        d = rgf.rgf_device(3, M, fake, fake, fake, fake, lead, lead)
+        rc = L.rgf_transmission_noalloc(C.byref(d), fake, 4, 1e-6, 0, fake, None, None)
+        assert rc == rgf.RGF_ETOOBIG, (M, rc)
+        assert b"scratch" in L.rgf_last_error()
+    assert L.rgf_transmission_noalloc(None, None, 0, 1e-6, 0, None, None, None) == rgf.RGF_EINVAL
+
+
 def test_binding_rejects_wrong_dtypes():
     """The binding checks what the C calls read and write through each pointer (CPU tensors are
     refused before any dtype question, so this runs without a GPU)."""
