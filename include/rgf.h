@@ -280,8 +280,13 @@ int rgf_kpm_dos(const double* mu, int32_t n_mom, double e_min, double e_max, con
 /*
  * lead_self_energy -- Sigma of one lead for side RGF_LEFT (L g_L U) or
  * RGF_RIGHT (U g_R L), written to sigma[nE][M][M] (device pointer, row-major,
- * device-side block).  Same pointer, stream and info conventions as
- * rgf_transmission; info bits 1/2 flag decimation that hit the iteration cap.
+ * device-side block).  The paper takes the electrode self-energies from the
+ * bulk electrode's Hamiltonian (Introduction; Abstract); here the lead's
+ * surface Green's function comes from Sancho-Rubio decimation of its
+ * principal layer and Sigma = L g U (left) or U g L (right) with
+ * U = z S01 - H01, L = z S01^+ - H01^+.  Same pointer, stream and info
+ * conventions as rgf_transmission; info bits 1/2 flag decimation that hit the
+ * iteration cap.
  */
 int lead_self_energy(const rgf_lead* lead, int side, const double* E, int64_t nE, double eta,
                      int precision, rgf_z* sigma, int32_t* info, void* stream);

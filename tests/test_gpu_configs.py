@@ -62,7 +62,7 @@ def c2_dev():
 
 def _precision_param():
     return pytest.mark.parametrize("precision", [
-        "fp64", pytest.param("mixed", marks=pytest.mark.xfail(strict=False, reason=MIXED_UNMET))])
+        "fp64", pytest.param("mixed", marks=pytest.mark.xfail(strict=True, reason=MIXED_UNMET))])
 
 
 @_precision_param()

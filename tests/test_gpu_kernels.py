@@ -1,7 +1,9 @@
 """Single-kernel checks on the GPU through the test-only harness library.
 
 The block product is compared with a plain product computed on the CPU
-(complex128 numpy); the Gauss-Jordan solve with ``numpy.linalg.solve``.
+(complex128 numpy); the blocked LU with partial pivoting and its two block
+triangular solves with ``numpy.linalg.solve``; the adjoint formation kernel
+with the element-wise fill and numpy.
 """
 import ctypes as C
 import os
