@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--sweep-variants", action="store_true",
                     help="kernels: the sweep products with each operand form, FP64 and FP32")
     ap.add_argument("--fp32", action="store_true", help="kernels: FP32 matrix cores (the mixed form)")
+    ap.add_argument("--fused", action="store_true",
+                    help="kernels: also compare the fused factor-and-solve with the batched LU at Mp <= 256")
     ap.add_argument("--requests", type=int, default=16, help="serve: requests in the mix")
     ap.add_argument("--slots", type=int, default=4, help="serve: server slots (worker streams)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -409,6 +411,7 @@ CLASS_NAMES = {
     "panel": "LU panels: pivot search and in-panel elimination (vector units, no matrix-core flops)",
     "lead": "decimation and self-energy products and panels",
     "other": "final block inverse, G_1N and trace products",
+    "fused": "fused factor-and-solve of the sweep, one workgroup per energy (padded block sizes up to 192)",
 }
 
 
@@ -474,13 +477,24 @@ def run_kernel_timing(args) -> int:
                   f"{fl / ms.value / 1e9:.1f} TFLOP/s | rc={rc}", flush=True)
         return 0
     prec = 1 if args.fp32 else 0
+    f, sv = C.c_double(), C.c_double()
+    if args.fused:
+        # X = B^-1 Y at the small block sizes: batched LU + two solves against the fused kernel
+        lib.rgf_ktest_gj_time.argtypes = [C.c_int] * 4 + [C.POINTER(C.c_double)]
+        g = C.c_double()
+        for Mp in (64, 128, 192, 256):
+            for batch in (64, 256, 784):
+                rc1 = lib.rgf_ktest_lu_time(0, Mp, Mp, batch, 3, C.byref(f), C.byref(sv))
+                rc2 = lib.rgf_ktest_gj_time(Mp, Mp, batch, 3, C.byref(g))
+                print(f"| Mp={Mp} | {batch} | LU+solves {f.value + sv.value:.3f} ms | fused {g.value:.3f} ms | "
+                      f"rc={rc1},{rc2}", flush=True)
+        return 0
     for tile, rows, cols, K, batch, inplace, label in (shapes[8:9] if args.only_product else shapes):
         rc = lib.rgf_ktest_gemm_time(prec, tile, rows, cols, K, batch, inplace, 5, C.byref(ms))
         fl = 8.0 * rows * cols * K * batch
         print(f"| {label} | {ms.value * 1e3:.1f} | {fl / ms.value / 1e9:.1f} | rc={rc}", flush=True)
     if args.only_product:
         return 0
-    f, sv = C.c_double(), C.c_double()
     for Mp in (256, 512, 1024):
         rc = lib.rgf_ktest_lu_time(prec, Mp, Mp, 64, 3, C.byref(f), C.byref(sv))
         print(f"LU Mp={Mp}, 64 energies: factor {f.value:.2f} ms, solves {sv.value:.2f} ms rc={rc}", flush=True)

@@ -403,6 +403,8 @@ int rgf_profile_read(int64_t* launches, double* total_ms, double* flops);
  *                       self-energies
  *   RGF_PROF_OTHER      the remaining products (final block inverse, its
  *                       refinement, G_1N and the trace products)
+ *   RGF_PROF_FUSED      the sweep's fused factor-and-solve launches at padded
+ *                       block sizes up to 192 (one workgroup per energy)
  * RGF_EINVAL for n < 0, unknown mask bits or an unknown class.
  */
 enum {
@@ -413,7 +415,8 @@ enum {
   RGF_PROF_PANEL = 4,
   RGF_PROF_LEAD = 5,
   RGF_PROF_OTHER = 6,
-  RGF_PROF_COUNT = 7
+  RGF_PROF_FUSED = 7,
+  RGF_PROF_COUNT = 8
 };
 int rgf_profile_classes(int every, uint32_t classes);
 int rgf_profile_read_class(int cls, int64_t* launches, double* total_ms, double* flops, int64_t* launches_all,

@@ -84,6 +84,13 @@ class Engine {
 
  private:
   MatRef mref(z64* p, int64_t ld, int64_t bstride, const int32_t* ridx = nullptr) const;
+  // X = T^-1 Y for every batch entry (T destroyed).  The right-hand sides are written into Y by
+  // the fills `rhs` (their destination and shape set, no row gather).  Returns Y as the block
+  // products should read X: through the pivot rows (fused path) or as it stands (LU path).
+  // `fusable`: the fused Gauss-Jordan kernel may serve this solve (the sweep's); the decimation
+  // iterates on blocks whose conditioning degrades, where LU with substitution keeps more digits.
+  MatRef factor_solve(z64* T, z64* Y, int64_t yld, int64_t ybs, int nrhs, std::vector<FillArgs> rhs,
+                      const int32_t* skip, int32_t code, int lp, int tp, int tile, bool fusable);
   double gemm(GemmArgs g, int prec, bool timed);
   void ldos_pass(const rgf_device& d, z64* store, const double* twos, z64* sblk, bool forward, double* dos,
                  double* inj);
@@ -98,6 +105,7 @@ class Engine {
 
   hipStream_t st_;
   int prec_, M_, Mp_, B_;
+  bool fused_;  // padded blocks up to 192: one fused factor-and-solve launch per sweep solve
   const double* E_;
   const double *EL_, *ER_;  // lead energies per side (E_ unless shifted)
   double eta_;

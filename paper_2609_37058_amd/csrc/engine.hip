@@ -26,6 +26,7 @@
 // 40 M^3 when every g_i is inverted and multiplied out.  No per-layer state
 // is kept beyond B, X and W, so memory per energy does not grow with N.
 #include <algorithm>
+#include <cstdlib>
 
 #include "engine.h"
 
@@ -66,10 +67,22 @@ Layout Layout::make(int Mp, int batch) {
   return l;
 }
 
+// The sweep's solves at padded block sizes up to 192 take the fused factor-and-solve: measured
+// against the batched LU and triangular solves (X = B^-1 U, 64 / 256 / 784 energies) it is
+// 2.5-4.3x faster at Mp = 64, 1.4-2.0x at 128 and 1.04-1.26x at 192, but 0.72-0.80x at 256,
+// where its K = 16 updates make it HBM-bound.  RGF_FUSED=0 in the environment selects the
+// batched LU everywhere.
+constexpr int FUSED_MAX_MP = 192;
+static bool fused_for(int Mp) {
+  if (Mp > FUSED_MAX_MP) return false;
+  const char* s = std::getenv("RGF_FUSED");
+  return !(s && std::atoi(s) == 0);
+}
+
 Engine::Engine(char* arena, const Layout& lay, hipStream_t st, int prec, int M, const double* E, double eta,
                int32_t* host_active)
-    : st_(st), prec_(prec), M_(M), Mp_(lay.Mp), B_(lay.batch), E_(E), EL_(E), ER_(E), eta_(eta),
-      host_active_(host_active) {
+    : st_(st), prec_(prec), M_(M), Mp_(lay.Mp), B_(lay.batch), fused_(fused_for(lay.Mp)), E_(E), EL_(E), ER_(E),
+      eta_(eta), host_active_(host_active) {
   MM_ = (int64_t)Mp_ * Mp_;
   nblk_sr_ = lay.nblk_sr;
   const int64_t U = (int64_t)B_ * MM_;
@@ -118,6 +131,40 @@ MatRef Engine::mref(z64* p, int64_t ld, int64_t bstride, const int32_t* ridx) co
   return mat(p, bstride, ld, ridx, ridx ? Mp_ : 0);
 }
 
+MatRef Engine::factor_solve(z64* T, z64* Y, int64_t yld, int64_t ybs, int nrhs, std::vector<FillArgs> rhs,
+                            const int32_t* skip, int32_t code, int lp, int tp, int tile, bool fusable) {
+  if (fused_ && fusable) {
+    for (FillArgs& f : rhs) launch_fill(f, B_, st_);
+    GjArgs a;
+    a.T = T;
+    a.tbs = MM_;
+    a.Y = Y;
+    a.ybs = ybs;
+    a.nrhs = nrhs;
+    a.Mp = Mp_;
+    a.perm = lu_.perm;
+    a.perm_bs = Mp_;
+    a.sing = sing_;
+    a.sing_code = code;
+    a.skip = skip;
+    launch_gj(a, B_, st_);
+    return mref(Y, yld, ybs, lu_.perm);
+  }
+  lu_factor(lu_, T, MM_, Mp_, B_, skip, code, lp, tile, st_);
+  for (FillArgs& f : rhs) {  // the right-hand sides in pivot order
+    if (f.kind == FILL_MAT) {
+      f.src.rowidx = lu_.perm;
+      f.src.ridx_bstride = Mp_;
+    } else {
+      f.ridx = lu_.perm;
+      f.ridx_bs = Mp_;
+    }
+    launch_fill(f, B_, st_);
+  }
+  lu_solve(lu_, T, MM_, Mp_, Y, ybs, nrhs, B_, skip, tp, tile, st_);
+  return mref(Y, yld, ybs);
+}
+
 double Engine::gemm(GemmArgs g, int prec, bool timed) {
   return launch_gemm(g, prec, tile_for(prec, Mp_), st_, timed ? 1 : 0);
 }
@@ -153,19 +200,18 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
     c.src = mref(eps_, Mp, MM_);
     c.ctl.skip = done;
     launch_fill(c, B_, st_);
-    lu_factor(lu_, Tsr_, MM_, Mp, B_, done, SING_LEAD, PREC_F64, tile, st_);
-    c = fill_args(mref(Ysr_, 2 * Mp, 2 * MM_), Mp, Mp, FILL_MAT);
-    c.src = mref(AB_, Mp, 2 * MM_, lu_.perm);
-    c.ctl.skip = done;
-    launch_fill(c, B_, st_);
-    c.dst = mref(Ysr_ + Mp, 2 * Mp, 2 * MM_);
-    c.src = mref(AB_ + MM_, Mp, 2 * MM_, lu_.perm);
-    launch_fill(c, B_, st_);
-    lu_solve(lu_, Tsr_, MM_, Mp, Ysr_, 2 * MM_, 2 * Mp, B_, done, PREC_F64, tile, st_);
+    FillArgs ra = fill_args(mref(Ysr_, 2 * Mp, 2 * MM_), Mp, Mp, FILL_MAT);
+    ra.src = mref(AB_, Mp, 2 * MM_);
+    ra.ctl.skip = done;
+    FillArgs rb = ra;
+    rb.dst = mref(Ysr_ + Mp, 2 * Mp, 2 * MM_);
+    rb.src = mref(AB_ + MM_, Mp, 2 * MM_);
+    const MatRef Xab = factor_solve(Tsr_, Ysr_, 2 * Mp, 2 * MM_, 2 * Mp, {ra, rb}, done, SING_LEAD, PREC_F64,
+                                    PREC_F64, tile, false);
     // the four products [alpha; beta] [Xa Xb]
     GemmArgs g = gemm_args(2 * Mp, 2 * Mp, Mp, B_);
     g.A = mref(AB_, Mp, 2 * MM_);
-    g.B = mref(Ysr_, 2 * Mp, 2 * MM_);
+    g.B = Xab;
     g.C = mref(C_, 2 * Mp, 4 * MM_);
     g.ctl.skip = done;
     gemm(g, PREC_F64, false);
@@ -197,19 +243,16 @@ void Engine::self_energy(const rgf_lead& lead, bool left, z64* out) {
   FillArgs f = fill_args(mref(Tsr_, Mp, MM_), Mp, Mp, FILL_MAT);
   f.src = mref(left ? epsL_ : epsR_, Mp, MM_);
   launch_fill(f, B_, st_);
-  lu_factor(lu_, Tsr_, MM_, Mp, B_, nullptr, SING_LEAD, PREC_F64, tile, st_);
-  // RHS: U of the lead (left side) or L (right side), rows gathered by the pivots
+  // RHS: U of the lead (left side) or L (right side)
   f = fill_args(mref(Ysr_, Mp, 2 * MM_), Mp, Mp, FILL_FORM);
   const double* El = left ? EL_ : ER_;
   f.f = gform(form(lead.H01, lead.S01, M_, /*conj_t=*/!left, false, El, eta_));
-  f.ridx = lu_.perm;
-  f.ridx_bs = Mp;
-  launch_fill(f, B_, st_);
-  lu_solve(lu_, Tsr_, MM_, Mp, Ysr_, 2 * MM_, Mp, B_, nullptr, PREC_F64, tile, st_);
+  const MatRef X =
+      factor_solve(Tsr_, Ysr_, Mp, 2 * MM_, Mp, {f}, nullptr, SING_LEAD, PREC_F64, PREC_F64, tile, false);
   GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
   g.a_kind = SRC_FORM;
   g.Af = gform(form(lead.H01, lead.S01, M_, /*conj_t=*/left, false, El, eta_));
-  g.B = mref(Ysr_, Mp, 2 * MM_);
+  g.B = X;
   g.C = mref(out, Mp, MM_);
   gemm(g, PREC_F64, false);
 }
@@ -230,7 +273,7 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
   const int lp = (mask & 2) ? PREC_F32 : PREC_F64;
   const int tp = (mask & 4) ? PREC_F32 : PREC_F64;
   const int tile = tile_for(sp, Mp_);
-  const MatRef X = mref(Y_, Mp, MM_);
+  MatRef X = mref(Y_, Mp, MM_);
 
   // B_0 = A_00 - Sigma_L (- Sigma_R when N = 1)
   FillArgs f = fill_args(mref(T_, Mp, MM_), Mp, Mp, FILL_FORM);
@@ -247,13 +290,9 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
   z64* Wnxt = Wb_;
   for (int l = 0; l + 1 < N; ++l) {
     // X = B_l^-1 U_l
-    lu_factor(lu_, T_, MM_, Mp, B_, nullptr, l + 1, lp, tile, st_);
     f = fill_args(mref(Y_, Mp, MM_), Mp, Mp, FILL_FORM);
     f.f = gform(form(d.Hu + l * M2, d.Su + l * M2, M_, false, false, E_, eta_));
-    f.ridx = lu_.perm;
-    f.ridx_bs = Mp;
-    launch_fill(f, B_, st_);
-    lu_solve(lu_, T_, MM_, Mp, Y_, MM_, Mp, B_, nullptr, tp, tile, st_);
+    X = factor_solve(T_, Y_, Mp, MM_, Mp, {f}, nullptr, l + 1, lp, tp, tile, true);
     if (l == 0) {
       FillArgs c = fill_args(mref(Wcur, Mp, MM_), Mp, Mp, FILL_MAT);
       c.src = X;
@@ -292,12 +331,8 @@ void Engine::sweep_and_trace(const rgf_device& d, double* T, int32_t* info, bool
     c.src = mref(T_, Mp, MM_);
     launch_fill(c, B_, st_);
   }
-  lu_factor(lu_, T_, MM_, Mp, B_, nullptr, N + 1, lp, tile, st_);
   f = fill_args(mref(Y_, Mp, MM_), Mp, Mp, FILL_IDENTITY);
-  f.ridx = lu_.perm;
-  f.ridx_bs = Mp;
-  launch_fill(f, B_, st_);
-  lu_solve(lu_, T_, MM_, Mp, Y_, MM_, Mp, B_, nullptr, tp, tile, st_);
+  X = factor_solve(T_, Y_, Mp, MM_, Mp, {f}, nullptr, N + 1, lp, tp, tile, true);
   MatRef ginv = X;
   if (refine) {
     // one Newton-Schulz step in FP64: g <- g + g (I - B g)

@@ -87,6 +87,7 @@ enum {
   PC_PANEL = RGF_PROF_PANEL,
   PC_LEAD = RGF_PROF_LEAD,
   PC_OTHER = RGF_PROF_OTHER,
+  PC_FUSED = RGF_PROF_FUSED,
   PC_COUNT = RGF_PROF_COUNT
 };
 bool profiling();
@@ -153,6 +154,26 @@ void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int
 // Y <- U^-1 L^-1 Y in place (Y = P RHS already gathered; Mp x nrhs per batch, ld nrhs).
 void lu_solve(const LuBufs& g, z64* T, int64_t bs, int Mp, z64* Y, int64_t ybs, int nrhs, int batch,
               const int32_t* skip, int prec, int tile, hipStream_t st);
+
+// Fused factor-and-solve for padded block sizes up to GJ_MAX_MP: X = B^-1 Y per batch entry
+// in one launch (one workgroup per entry; blocked Gauss-Jordan with partial pivoting, rows in
+// place).  B is destroyed; Y is overwritten so that row perm[j] of Y holds row j of X.
+constexpr int GJ_MAX_MP = 256;
+struct GjArgs {
+  z64* T;            // B, Mp x Mp (ld Mp) per entry
+  int64_t tbs;       // batch stride of T
+  z64* Y;            // right-hand sides, Mp x nrhs (ld nrhs) per entry
+  int64_t ybs;       // batch stride of Y
+  int nrhs;          // multiple of 16
+  int Mp;            // 64, 128, 192 or 256
+  int32_t* perm;     // out: Mp per entry
+  int64_t perm_bs;
+  int32_t* sing;     // per entry: first singular event code (0 = none)
+  int32_t sing_code;
+  const int32_t* skip;  // entries to leave alone (null: none)
+};
+// returns the matrix-core flops launched
+double launch_gj(const GjArgs& a, int batch, hipStream_t st);
 
 // ---------------------------------------------------------- elementwise
 enum { FILL_ZERO = 0, FILL_IDENTITY = 1, FILL_MAT = 2, FILL_FORM = 3 };

@@ -89,6 +89,59 @@ int rgf_ktest_lu(int prec, int Mp, int nrhs, int batch, void* B, const void* RHS
   });
 }
 
+// X[b] = B[b]^-1 Y[b] by the fused factor-and-solve kernel (one workgroup per entry): B (Mp x Mp)
+// is destroyed, Y (Mp x nrhs) is overwritten in pivot-row order; X (Mp x nrhs) receives the
+// solution gathered through the pivot rows.  skip (host, may be null): entries left alone.
+int rgf_ktest_gj(int Mp, int nrhs, int batch, void* B, void* Y, void* X, const int32_t* skip_host,
+                 int32_t* perm_out, int32_t* sing_out) {
+  return kt_guard([&] {
+    int32_t *perm = nullptr, *sing = nullptr, *skip = nullptr;
+    RGF_HIP(hipMalloc((void**)&perm, sizeof(int32_t) * batch * Mp));
+    RGF_HIP(hipMalloc((void**)&sing, sizeof(int32_t) * batch));
+    RGF_HIP(hipMemset(sing, 0, sizeof(int32_t) * batch));
+    RGF_HIP(hipMemset(perm, 0, sizeof(int32_t) * batch * Mp));
+    if (skip_host) {
+      RGF_HIP(hipMalloc((void**)&skip, sizeof(int32_t) * batch));
+      RGF_HIP(hipMemcpy(skip, skip_host, sizeof(int32_t) * batch, hipMemcpyHostToDevice));
+    }
+    const int64_t bs = (int64_t)Mp * Mp, ybs = (int64_t)Mp * nrhs;
+    GjArgs a;
+    a.T = (z64*)B;
+    a.tbs = bs;
+    a.Y = (z64*)Y;
+    a.ybs = ybs;
+    a.nrhs = nrhs;
+    a.Mp = Mp;
+    a.perm = perm;
+    a.perm_bs = Mp;
+    a.sing = sing;
+    a.sing_code = 7;
+    a.skip = skip;
+    launch_gj(a, batch, nullptr);
+    FillArgs f;
+    f.dst = mat((z64*)X, ybs, nrhs);
+    f.rows = Mp;
+    f.cols = nrhs;
+    f.kind = FILL_MAT;
+    f.scale = 1.0;
+    f.src = mat((z64*)Y, ybs, nrhs, perm, Mp);
+    f.f = form(nullptr, nullptr, 0, false, false, nullptr, 0.0);
+    f.flags = nullptr;
+    f.flags_bs = 0;
+    f.flags_n = 0;
+    f.ridx = nullptr;
+    f.ridx_bs = 0;
+    f.ctl.skip = skip;
+    launch_fill(f, batch, nullptr);
+    RGF_HIP(hipDeviceSynchronize());
+    if (perm_out) RGF_HIP(hipMemcpy(perm_out, perm, sizeof(int32_t) * batch * Mp, hipMemcpyDeviceToHost));
+    if (sing_out) RGF_HIP(hipMemcpy(sing_out, sing, sizeof(int32_t) * batch, hipMemcpyDeviceToHost));
+    RGF_HIP(hipFree(perm));
+    RGF_HIP(hipFree(sing));
+    if (skip) RGF_HIP(hipFree(skip));
+  });
+}
+
 // Pseudo-random complex entries in [-1, 1) plus `diag` on the diagonal (timing inputs).
 __global__ void kt_fill_random(z64* p, int64_t n, int64_t ld, int64_t rows_per_batch, double diag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -199,6 +252,54 @@ int rgf_ktest_lu_time(int prec, int Mp, int nrhs, int batch, int reps, double* m
     for (void* q : {(void*)g.linv, (void*)g.uinv, (void*)g.perm, (void*)g.cand, (void*)g.flags, (void*)g.sing,
                     (void*)B0, (void*)B, (void*)Y})
       RGF_HIP(hipFree(q));
+  });
+}
+
+// Average duration (ms, HIP events) of one fused factor-and-solve launch on random diagonally
+// weighted B (Mp x Mp) and Y (Mp x nrhs), `batch` entries.
+int rgf_ktest_gj_time(int Mp, int nrhs, int batch, int reps, double* ms) {
+  return kt_guard([&] {
+    z64 *B0, *B, *Y0, *Y;
+    int32_t *perm, *sing;
+    const int64_t bs = (int64_t)Mp * Mp, ybs = (int64_t)Mp * nrhs;
+    RGF_HIP(hipMalloc((void**)&B0, sizeof(z64) * batch * bs));
+    RGF_HIP(hipMalloc((void**)&B, sizeof(z64) * batch * bs));
+    RGF_HIP(hipMalloc((void**)&Y0, sizeof(z64) * batch * ybs));
+    RGF_HIP(hipMalloc((void**)&Y, sizeof(z64) * batch * ybs));
+    RGF_HIP(hipMalloc((void**)&perm, sizeof(int32_t) * batch * Mp));
+    RGF_HIP(hipMalloc((void**)&sing, sizeof(int32_t) * batch));
+    RGF_HIP(hipMemset(sing, 0, sizeof(int32_t) * batch));
+    kt_random(B0, batch * bs, Mp, Mp, 4.0);
+    kt_random(Y0, batch * ybs, nrhs, Mp, 0.0);
+    GjArgs a;
+    a.T = B;
+    a.tbs = bs;
+    a.Y = Y;
+    a.ybs = ybs;
+    a.nrhs = nrhs;
+    a.Mp = Mp;
+    a.perm = perm;
+    a.perm_bs = Mp;
+    a.sing = sing;
+    a.sing_code = 1;
+    a.skip = nullptr;
+    hipEvent_t e[2];
+    for (auto& x : e) RGF_HIP(hipEventCreate(&x));
+    double t = 0.0;
+    for (int r = 0; r <= reps; ++r) {
+      RGF_HIP(hipMemcpy(B, B0, sizeof(z64) * batch * bs, hipMemcpyDeviceToDevice));
+      RGF_HIP(hipMemcpy(Y, Y0, sizeof(z64) * batch * ybs, hipMemcpyDeviceToDevice));
+      RGF_HIP(hipEventRecord(e[0], nullptr));
+      launch_gj(a, batch, nullptr);
+      RGF_HIP(hipEventRecord(e[1], nullptr));
+      RGF_HIP(hipEventSynchronize(e[1]));
+      float x = 0.f;
+      RGF_HIP(hipEventElapsedTime(&x, e[0], e[1]));
+      if (r > 0) t += x;
+    }
+    *ms = t / reps;
+    for (auto& x : e) RGF_HIP(hipEventDestroy(x));
+    for (void* q : {(void*)B0, (void*)B, (void*)Y0, (void*)Y, (void*)perm, (void*)sing}) RGF_HIP(hipFree(q));
   });
 }
 

@@ -454,7 +454,7 @@ def profile_read() -> Tuple[int, float, float]:
 
 
 #: kernel classes of rgf_profile_classes (include/rgf.h, RGF_PROF_*)
-PROFILE_CLASSES = ("sweep", "lu_update", "solve", "row64", "panel", "lead", "other")
+PROFILE_CLASSES = ("sweep", "lu_update", "solve", "row64", "panel", "lead", "other", "fused")
 
 
 def profile_classes(enable: bool, every: int = 1, classes=PROFILE_CLASSES):

@@ -66,11 +66,11 @@ def test_argument_errors_before_device_work(lib):
     assert L.rgf_set_checks(1) == rgf.RGF_OK and L.rgf_get_checks() == 1
     assert L.rgf_set_checks(0) == rgf.RGF_OK and L.rgf_get_checks() == 0
     assert L.rgf_profile(16) == rgf.RGF_OK and L.rgf_profile(0) == rgf.RGF_OK
-    assert L.rgf_profile_classes(1, 1 << 7) == rgf.RGF_EINVAL  # no class 7
+    assert L.rgf_profile_classes(1, 1 << 8) == rgf.RGF_EINVAL  # no class 8
     assert L.rgf_profile_classes(-1, 1) == rgf.RGF_EINVAL
-    assert L.rgf_profile_classes(3, (1 << 7) - 1) == rgf.RGF_OK and L.rgf_profile_classes(0, 0) == rgf.RGF_OK
+    assert L.rgf_profile_classes(3, (1 << 8) - 1) == rgf.RGF_OK and L.rgf_profile_classes(0, 0) == rgf.RGF_OK
     n = C.c_int64()
-    assert L.rgf_profile_read_class(7, C.byref(n), None, None, None, None) == rgf.RGF_EINVAL
+    assert L.rgf_profile_read_class(8, C.byref(n), None, None, None, None) == rgf.RGF_EINVAL
 
 
 def test_decimation_cap_setting(lib):

@@ -30,6 +30,7 @@ def kt():
     lib.rgf_ktest_lu.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p]
     lib.rgf_ktest_form_ct.argtypes = [C.c_int] * 5 + [C.c_void_p] * 3 + [C.c_double, C.c_void_p, C.c_void_p]
+    lib.rgf_ktest_gj.argtypes = [C.c_int] * 3 + [C.c_void_p] * 6
     return lib
 
 
@@ -117,3 +118,59 @@ def test_adjoint_formation_kernel(kt, M, Mp, batch, groups, pad):
         ref[:M, :M] = (E[b] + 1j * eta) * S[g].conj().T - H[g].conj().T
         assert np.allclose(oc[b], ref, rtol=0, atol=1e-14 * (1 + np.abs(ref).max()))
         assert np.array_equal(oc[b][M:, :], ref[M:, :]) and np.array_equal(oc[b][:, M:], ref[:, M:])
+
+
+@pytest.mark.parametrize("Mp,rhs,batch", [(64, 1, 3), (64, 2, 2), (128, 1, 3), (128, 2, 2), (192, 1, 2),
+                                          (256, 1, 3), (256, 2, 2)])
+def test_fused_factor_solve_matches_numpy_solve(kt, Mp, rhs, batch):
+    """The fused Gauss-Jordan factor-and-solve (one workgroup per entry) against numpy.linalg.solve,
+    with rows scaled so that partial pivoting must reorder them, nrhs = Mp and 2 Mp; the pivot rows
+    are a permutation; entry 1 is skipped and must come back untouched."""
+    import torch
+    nrhs = rhs * Mp
+    rng = np.random.default_rng(7 * Mp + nrhs)
+    Bm = _rand(rng, (batch, Mp, Mp))
+    Bm *= np.exp(rng.uniform(-3, 3, size=(batch, Mp, 1)))
+    R = _rand(rng, (batch, Mp, nrhs))
+    tb = torch.as_tensor(np.ascontiguousarray(Bm)).cuda()
+    ty = torch.as_tensor(np.ascontiguousarray(R)).cuda()
+    X = torch.zeros((batch, Mp, nrhs), dtype=torch.complex128, device="cuda")
+    perm = np.zeros((batch, Mp), np.int32)
+    sing = np.zeros(batch, np.int32)
+    skip = np.zeros(batch, np.int32)
+    skip[1] = 1
+    log(f"[kernel] fused gj Mp={Mp} nrhs={nrhs} b={batch}")
+    rc = kt.rgf_ktest_gj(Mp, nrhs, batch, tb.data_ptr(), ty.data_ptr(), X.data_ptr(), skip.ctypes.data,
+                         perm.ctypes.data, sing.ctypes.data)
+    assert rc == 0
+    got = X.cpu().numpy()
+    ref = np.linalg.solve(Bm, R)
+    for b in range(batch):
+        if b == 1:
+            assert np.array_equal(tb[1].cpu().numpy(), Bm[1]) and np.array_equal(ty[1].cpu().numpy(), R[1])
+            continue
+        err = np.max(np.abs(got[b] - ref[b])) / np.max(np.abs(ref[b]))
+        log(f"[kernel]   entry {b}: rel err {err:.2e}")
+        assert err < 1e-11
+        assert sorted(perm[b].tolist()) == list(range(Mp))
+    assert np.all(sing == 0)
+
+
+def test_fused_factor_solve_flags_exact_zero_pivot(kt):
+    """An all-zero column makes an exactly zero pivot: the entry's singular code is set (and only
+    that entry's); the kernel finishes normally."""
+    import torch
+    Mp, nrhs, batch = 128, 128, 2
+    rng = np.random.default_rng(3)
+    Bm = _rand(rng, (batch, Mp, Mp))
+    Bm[0, :, 40] = 0.0
+    R = _rand(rng, (batch, Mp, nrhs))
+    tb = torch.as_tensor(np.ascontiguousarray(Bm)).cuda()
+    ty = torch.as_tensor(np.ascontiguousarray(R)).cuda()
+    X = torch.zeros((batch, Mp, nrhs), dtype=torch.complex128, device="cuda")
+    sing = np.zeros(batch, np.int32)
+    rc = kt.rgf_ktest_gj(Mp, nrhs, batch, tb.data_ptr(), ty.data_ptr(), X.data_ptr(), None, None, sing.ctypes.data)
+    assert rc == 0
+    assert sing[0] == 7 and sing[1] == 0
+    got = X.cpu().numpy()
+    assert np.max(np.abs(got[1] - np.linalg.solve(Bm[1], R[1]))) < 1e-10 * np.max(np.abs(got[1]))
