@@ -18,14 +18,25 @@
 //
 // Work split: a BM x BN output tile per workgroup of WGM x WGN wavefronts,
 // each wavefront owning a (BM/WGM) x (BN/WGN) block of 16x16 MFMA tiles.
-// K advances 16 complex columns per LDS stage, with two LDS stages: the
+// K advances BK complex columns per LDS stage, with two LDS stages: the
 // next stage's global loads are issued before the current stage's MFMAs and
 // written to the other LDS stage after them, so one barrier per stage
 // suffices and HBM/L2 latency hides behind the (64-cycle) FP64 MFMAs.
+// Products with a short inner dimension (the LU's trailing updates and
+// 64-row blocks, K <= 128) spend as long reading and writing C as in their
+// MFMAs.  With the 128 x 128 tile (8 wavefronts, BK = 16, 132 KB of LDS in
+// FP64) one workgroup fills a CU and those phases cannot overlap, so such
+// products take 128 x 64 (or 64 x 128) tiles of 4 wavefronts with BK = 8:
+// 50 KB of LDS and two workgroups per CU, whose C traffic and MFMAs
+// interleave.  Every output element still sums its K terms in the same order,
+// so the choice of tile does not change a result.
 // Shapes are multiples of 64; a 128-wide tile that overhangs the matrix
 // leaves its outer wavefront blocks idle.  Tiles are handed out so that
 // each of the 8 XCDs works on a contiguous range of (batch, row-tile,
 // col-tile) ids: the operands of one batch entry stay in one XCD's L2.
+#include <atomic>
+#include <cstdlib>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -35,7 +46,8 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int BK = 16;
+// inner-dimension granularity every launch must respect (the largest stage depth)
+constexpr int K_ALIGN = 16;
 
 template <typename R>
 struct CT;
@@ -64,8 +76,22 @@ struct CT<float> {
   __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-// Element (r, c) of the Cin operand of batch entry b (a matrix or a formed
-// block whose blocks start coff elements after Cf's: a grouped batch).
+// Row offsets (in elements, from the batch entry's base) of the 4 output rows r0 + out_row(lane, v)
+// of a lane in one 16-row MFMA block row.  With a row gather the 4 index loads are issued
+// together, so a block row waits for memory once instead of once per element.
+template <typename R>
+__device__ inline void frag_rows(const MatRef& m, int b, int r0, int lane, int (&ro)[4]) {
+  if (m.rowidx) {
+    const int32_t* ri = m.rowidx + (int64_t)b * m.ridx_bstride;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ro[v] = ri[r0 + CT<R>::out_row(lane, v)];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ro[v] = r0 + CT<R>::out_row(lane, v);
+  }
+}
+
+// One element (r, c) of the Cin operand of batch entry b (FP32 epilogue; see c_quad).
 __device__ inline z64 c_value(const GemmArgs& g, int b, int r, int c, z64 zc, int64_t coff) {
   if (g.c_kind == SRC_MAT) return g.Cin.p[mat_off(g.Cin, b, r, c)];
   z64 f = zmake(0.0, 0.0);
@@ -82,12 +108,67 @@ __device__ inline z64 c_value(const GemmArgs& g, int b, int r, int c, z64 zc, in
   return f;
 }
 
+// Gathered rows of the C operand's stored source for one block row: Cin for a matrix operand,
+// the subtracted Sigma for a formed one (whose z S - H part is read at the logical rows).
+template <typename R>
+__device__ inline void c_src_rows(const GemmArgs& g, int b, int r0, int lane, int (&ro)[4]) {
+  if (g.c_kind == SRC_MAT) frag_rows<R>(g.Cin, b, r0, lane, ro);
+  else if (g.Cf.sub.p) frag_rows<R>(g.Cf.sub, b, r0, lane, ro);
+}
+
+// The Cin operand (a matrix, or a formed block z S - H with identity padding and an optional
+// -+ Sigma, whose blocks start coff elements after Cf's: a grouped batch) at the lane's 4
+// elements of one 16 x 16 block: rows r0 + out_row(lane, v), column c (FP64).  The quad's
+// loads are all issued before a scheduling barrier and used after it; otherwise the scheduler,
+// seeing the main loop's register pressure, issues each load just before its use and waits for
+// it, one memory latency per element.  Out-of-range formed elements read element 0 of the
+// blocks (when there are any) and discard it.  (The FP32 kernels, held to 128 VGPRs, have no
+// room for grouped loads and read Cin one element at a time in their epilogue.)
+template <typename R>
+__device__ inline void c_quad(const GemmArgs& g, int b, int r0, int c, int lane, int64_t coff, const int (&ro)[4],
+                              z64 (&cv)[4]) {
+  if (g.c_kind == SRC_MAT) {
+    const z64* base = g.Cin.p + (int64_t)b * g.Cin.bstride;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) cv[v] = base[(int64_t)ro[v] * g.Cin.ld + c];
+    __builtin_amdgcn_sched_barrier(0);
+    return;
+  }
+  const int M = g.Cf.M;
+  const z64* S = g.Cf.S + coff;
+  const z64* H = g.Cf.H + coff;
+  const z64* sb = g.Cf.sub.p ? g.Cf.sub.p + (int64_t)b * g.Cf.sub.bstride : nullptr;
+  z64 sv[4], hv[4], sg[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = r0 + CT<R>::out_row(lane, v);
+    const int64_t o = (r < M && c < M) ? (int64_t)r * M + c : 0;
+    // an operand without blocks (M = 0: the identity, S = H = null) reads nothing
+    sv[v] = M > 0 ? S[o] : zmake(0.0, 0.0);
+    hv[v] = M > 0 ? H[o] : zmake(0.0, 0.0);
+    if (sb) sg[v] = sb[(int64_t)ro[v] * g.Cf.sub.ld + c];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  const z64 zc = zmake(g.Cf.E[b], g.Cf.eta);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = r0 + CT<R>::out_row(lane, v);
+    z64 f = (r < M && c < M) ? zform(zc, sv[v], hv[v]) : zmake((g.Cf.pad_identity && r == c) ? 1.0 : 0.0, 0.0);
+    if (sb) f = zmake(f.x + g.Cf.sub_sign * sg[v].x, f.y + g.Cf.sub_sign * sg[v].y);
+    cv[v] = f;
+  }
+}
+
 // How the A operand is staged: a per-batch matrix, a formed block z S - H,
 // or the adjoint form z S^+ - H^+ (read transposed, so staged k-major).
 enum { AK_MAT = 0, AK_FORM = 1, AK_FORM_CT = 2 };
 
-template <typename R, int BM, int BN, int WGM, int WGN, int AK, int ROLE>
-__global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int tiles_m, int tiles_n) {
+// FP64: two wavefronts per SIMD (an 8-wavefront workgroup per CU, or two of 4 wavefronts).
+// FP32 with a stored A operand: four, so that two 8-wavefront workgroups share a CU (at most
+// 128 VGPRs); the formed-operand FP32 variants need more registers and stay at two.
+template <typename R, int BM, int BN, int WGM, int WGN, int BK, int AK, int ROLE>
+__global__ __launch_bounds__(64 * WGM * WGN, (!CT<R>::exact && AK == AK_MAT) ? 4 : 2) void zgemm_kernel(
+    GemmArgs g, int tiles_m, int tiles_n) {
   typedef typename CT<R>::c cR;
   typedef typename CT<R>::acc accT;
   constexpr int NT = 64 * WGM * WGN;
@@ -217,20 +298,23 @@ __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int t
   // loads overlap the first stage's loads instead of stalling the epilogue
   const bool c_pre = CT<R>::exact && g.c_kind != SRC_NONE && (g.alpha == 1.0 || g.alpha == -1.0);
   const int64_t c_off = form_group_off(g.Cf, b);
+  const int r_w = row0 + wm * WTM, c_w = col0 + wn * WTN + (lane & 15);
   if (c_pre && w_active) {
-    const z64 zc = (g.c_kind == SRC_FORM) ? zmake(g.Cf.E[b], g.Cf.eta) : zmake(0.0, 0.0);
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i) {
+      int ro[4];
+      c_src_rows<R>(g, b, r_w + 16 * i, lane, ro);
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
+      for (int j = 0; j < FN; ++j) {
+        z64 cv[4];
+        c_quad<R>(g, b, r_w + 16 * i, c_w + 16 * j, lane, c_off, ro, cv);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = row0 + wm * WTM + i * 16 + CT<R>::out_row(lane, v);
-          const int c = col0 + wn * WTN + j * 16 + (lane & 15);
-          const z64 cin = c_value(g, b, r, c, zc, c_off);
-          accr[i][j][v] = (R)(g.alpha * cin.x);
-          acci[i][j][v] = (R)(g.alpha * cin.y);
+          accr[i][j][v] = (R)(g.alpha * cv[v].x);
+          acci[i][j][v] = (R)(g.alpha * cv[v].y);
         }
+      }
+    }
   }
 
   const int nst = g.K / BK;
@@ -272,31 +356,58 @@ __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(GemmArgs g, int t
   if (!w_active) return;
 
   // ---- epilogue: C = Cin + alpha * acc ----
-  const z64 zc = (g.c_kind == SRC_FORM) ? zmake(g.Cf.E[b], g.Cf.eta) : zmake(0.0, 0.0);
+  z64* cbase = g.C.p + (int64_t)b * g.C.bstride;
+  if constexpr (CT<R>::exact) {
+    // the output rows' gathered indices first (one wait for the whole tile), then a 16-row
+    // block row at a time
+    int ro[FM][4];
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i) frag_rows<R>(g.C, b, r_w + 16 * i, lane, ro[i]);
+    __builtin_amdgcn_sched_barrier(0);
+    const bool c_post = !c_pre && g.c_kind != SRC_NONE;
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+    for (int i = 0; i < FM; ++i) {
+      int rs[4];
+      if (c_post) c_src_rows<R>(g, b, r_w + 16 * i, lane, rs);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = row0 + wm * WTM + i * 16 + CT<R>::out_row(lane, v);
-        const int c = col0 + wn * WTN + j * 16 + (lane & 15);
-        z64 out = zmake(g.alpha * (double)accr[i][j][v], g.alpha * (double)acci[i][j][v]);
-        if (!c_pre && g.c_kind != SRC_NONE) out = zadd(out, c_value(g, b, r, c, zc, c_off));
-        g.C.p[mat_off(g.C, b, r, c)] = out;
+      for (int j = 0; j < FN; ++j) {
+        z64 cv[4];
+        if (c_post) c_quad<R>(g, b, r_w + 16 * i, c_w + 16 * j, lane, c_off, rs, cv);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          z64 out = zmake(g.alpha * accr[i][j][v], g.alpha * acci[i][j][v]);
+          if (c_post) out = zadd(out, cv[v]);
+          cbase[(int64_t)ro[i][v] * g.C.ld + c_w + 16 * j] = out;
+        }
       }
+    }
+  } else {
+    const z64 zc = (g.c_kind == SRC_FORM) ? zmake(g.Cf.E[b], g.Cf.eta) : zmake(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = r_w + i * 16 + CT<R>::out_row(lane, v);
+          const int c = c_w + j * 16;
+          z64 out = zmake(g.alpha * (double)accr[i][j][v], g.alpha * (double)acci[i][j][v]);
+          if (g.c_kind != SRC_NONE) out = zadd(out, c_value(g, b, r, c, zc, c_off));
+          g.C.p[mat_off(g.C, b, r, c)] = out;
+        }
+  }
 }
 
-template <typename R, int BM, int BN, int WGM, int WGN, int AK>
+template <typename R, int BM, int BN, int WGM, int WGN, int BK, int AK>
 void launch_kind(const GemmArgs& g, dim3 grid, hipStream_t st, int role, int tm, int tn) {
   constexpr int NT = 64 * WGM * WGN;
   if (role == 1)
-    hipLaunchKernelGGL((zgemm_kernel<R, BM, BN, WGM, WGN, AK, 1>), grid, dim3(NT), 0, st, g, tm, tn);
+    hipLaunchKernelGGL((zgemm_kernel<R, BM, BN, WGM, WGN, BK, AK, 1>), grid, dim3(NT), 0, st, g, tm, tn);
   else
-    hipLaunchKernelGGL((zgemm_kernel<R, BM, BN, WGM, WGN, AK, 0>), grid, dim3(NT), 0, st, g, tm, tn);
+    hipLaunchKernelGGL((zgemm_kernel<R, BM, BN, WGM, WGN, BK, AK, 0>), grid, dim3(NT), 0, st, g, tm, tn);
 }
 
-template <typename R, int BM, int BN, int WGM, int WGN>
+template <typename R, int BM, int BN, int WGM, int WGN, int BK = 16>
 void launch_cfg(const GemmArgs& g, hipStream_t st, int role) {
   const int tm = (g.rows + BM - 1) / BM, tn = (g.cols + BN - 1) / BN;
   // a product written in place over its B operand must keep each column block in one workgroup
@@ -304,18 +415,21 @@ void launch_cfg(const GemmArgs& g, hipStream_t st, int role) {
   RGF_CHECK(!(in_place && tm > 1), RGF_EINVAL, "gemm: in-place product spans several row tiles");
   const dim3 grid((unsigned)((int64_t)tm * tn * g.batch));
   if (g.a_kind != SRC_FORM)
-    launch_kind<R, BM, BN, WGM, WGN, AK_MAT>(g, grid, st, role, tm, tn);
+    launch_kind<R, BM, BN, WGM, WGN, BK, AK_MAT>(g, grid, st, role, tm, tn);
   else if (g.Af.conj_t)
-    launch_kind<R, BM, BN, WGM, WGN, AK_FORM_CT>(g, grid, st, role, tm, tn);
+    launch_kind<R, BM, BN, WGM, WGN, BK, AK_FORM_CT>(g, grid, st, role, tm, tn);
   else
-    launch_kind<R, BM, BN, WGM, WGN, AK_FORM>(g, grid, st, role, tm, tn);
+    launch_kind<R, BM, BN, WGM, WGN, BK, AK_FORM>(g, grid, st, role, tm, tn);
 }
 
 // Tile choice depends only on the shape and the requested tile size, never on
 // the batch, so a result does not depend on which other energies share a launch.
 template <typename R>
 void launch_prec(const GemmArgs& g, int tile, hipStream_t st, int role) {
-  if (tile >= 128 && g.rows >= 128) {
+  if (tile >= 128 && g.K <= small_k_max()) {
+    if (g.rows >= 128) launch_cfg<R, 128, 64, 2, 2, 8>(g, st, role);
+    else launch_cfg<R, 64, 128, 1, 4, 8>(g, st, role);
+  } else if (tile >= 128 && g.rows >= 128) {
     launch_cfg<R, 128, 128, 2, 4>(g, st, role);
   } else if (tile >= 128) {
     launch_cfg<R, 64, 128, 2, 4>(g, st, role);
@@ -326,9 +440,26 @@ void launch_prec(const GemmArgs& g, int tile, hipStream_t st, int role) {
 
 }  // namespace
 
+static std::atomic<int> g_small_k_max{-1};
+int small_k_max() {
+  int k = g_small_k_max.load(std::memory_order_relaxed);
+  if (k < 0) {
+    k = 128;
+    if (const char* s = std::getenv("RGF_SMALLK_MAXK")) k = std::max(0, std::atoi(s));
+    int expect = -1;
+    if (!g_small_k_max.compare_exchange_strong(expect, k)) k = expect;
+  }
+  return k;
+}
+int set_small_k_max(int k) {
+  const int prev = small_k_max();
+  g_small_k_max.store(std::max(0, k));
+  return prev;
+}
+
 double launch_gemm(const GemmArgs& g, int prec, int tile, hipStream_t st, int role) {
   if (g.rows <= 0 || g.cols <= 0 || g.batch <= 0) return 0.0;
-  RGF_CHECK(g.K % BK == 0, RGF_EINVAL, "gemm: K not a multiple of 16");
+  RGF_CHECK(g.K % K_ALIGN == 0, RGF_EINVAL, "gemm: K not a multiple of 16");
   RGF_CHECK(g.rows % 64 == 0 && g.cols % 64 == 0, RGF_EINVAL, "gemm: shape not tiled");
   const double flops = 8.0 * g.rows * (double)g.cols * g.K * g.batch;
   const bool prof = profiling();

@@ -116,6 +116,10 @@ struct ProfLead {
 // products (a separate kernel symbol, so profiles can single them out).
 // Returns the algorithmic flops launched.
 double launch_gemm(const GemmArgs& g, int prec, int tile, hipStream_t st, int role = 0);
+// Largest inner dimension that takes the short-K product tiles (0: never).  Defaults to 128,
+// or RGF_SMALLK_MAXK from the environment; the setter returns the previous value.
+int small_k_max();
+int set_small_k_max(int k);
 
 // ------------------------------------------- LU with partial pivoting
 constexpr int LU_NB = 64;

@@ -386,4 +386,7 @@ int rgf_ktest_form_ct(int M, int Mp, int batch, int groups, int pad, const void*
   });
 }
 
+// Largest inner dimension that takes the short-K product tiles (0: never); returns the previous.
+int rgf_ktest_set_small_k(int k) { return set_small_k_max(k); }
+
 }  // extern "C"

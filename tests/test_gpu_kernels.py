@@ -31,6 +31,7 @@ def kt():
                                  C.c_void_p, C.c_void_p]
     lib.rgf_ktest_form_ct.argtypes = [C.c_int] * 5 + [C.c_void_p] * 3 + [C.c_double, C.c_void_p, C.c_void_p]
     lib.rgf_ktest_gj.argtypes = [C.c_int] * 3 + [C.c_void_p] * 6
+    lib.rgf_ktest_set_small_k.argtypes = [C.c_int]
     return lib
 
 
@@ -40,9 +41,11 @@ def _rand(rng, shape):
 
 @pytest.mark.parametrize("prec,tile", [(0, 64), (1, 64), (1, 128), (0, 128)])
 @pytest.mark.parametrize("rows,cols,K,batch", [(64, 64, 16, 1), (128, 64, 64, 3), (128, 256, 48, 2),
-                                               (192, 320, 32, 2), (320, 192, 80, 3), (64, 448, 64, 2)])
+                                               (192, 320, 32, 2), (320, 192, 80, 3), (64, 448, 64, 2),
+                                               (192, 192, 256, 2), (64, 320, 144, 2)])
 def test_gemm_matches_numpy(kt, prec, tile, rows, cols, K, batch):
-    """Shapes that are multiples of 64 but not of 128 run on 128-wide tiles that overhang the matrix."""
+    """Shapes that are multiples of 64 but not of 128 run on 128-wide tiles that overhang the matrix;
+    K <= 128 with 128-wide tiles takes the short-K tiles, the last two shapes the 8-wavefront ones."""
     import torch
     rng = np.random.default_rng(rows + cols + K + batch)
     A = _rand(rng, (batch, rows, K))
@@ -58,6 +61,35 @@ def test_gemm_matches_numpy(kt, prec, tile, rows, cols, K, batch):
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     log(f"[kernel] gemm rel err {err:.2e}")
     assert err < (1e-14 if prec == 0 else 2e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("rows,cols,K,batch", [(64, 1024, 64, 3), (960, 960, 64, 2), (896, 896, 128, 2),
+                                               (192, 320, 16, 2), (128, 64, 112, 3)])
+def test_short_k_tiles_bitwise_equal_to_wide_tiles(kt, prec, rows, cols, K, batch):
+    """The short-K tiles (4 wavefronts, 8-column stages) sum every output's K terms in the same
+    order as the 8-wavefront tiles, so the two give identical bits."""
+    import torch
+    rng = np.random.default_rng(7 * rows + cols + K)
+    A = _rand(rng, (batch, rows, K))
+    B = _rand(rng, (batch, K, cols))
+    C0 = _rand(rng, (batch, rows, cols))
+    ta, tb = (torch.as_tensor(x).cuda() for x in (A, B))
+    out = []
+    prev = kt.rgf_ktest_set_small_k(128)
+    try:
+        for k in (128, 0):
+            kt.rgf_ktest_set_small_k(k)
+            tc = torch.as_tensor(C0).cuda()
+            log(f"[kernel] short-K={k} prec={prec} {rows}x{cols}x{K} b={batch}")
+            assert kt.rgf_ktest_gemm(prec, 128, rows, cols, K, batch, ta.data_ptr(), tb.data_ptr(), tc.data_ptr(),
+                                     -1.0, 1) == 0
+            out.append(tc.cpu().numpy())
+    finally:
+        kt.rgf_ktest_set_small_k(prev)
+    assert np.array_equal(out[0], out[1])
+    ref = C0 - A @ B
+    assert np.max(np.abs(out[0] - ref)) / np.max(np.abs(ref)) < (1e-14 if prec == 0 else 2e-6)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
