@@ -294,8 +294,9 @@ __global__ __launch_bounds__(64 * WGM * WGN, (!CT<R>::exact && AK == AK_MAT) ? 4
         bs_[b_k * LDB + b_c + e] = CT<R>::cvt(b_ok ? rb[e] : zmake(0.0, 0.0));               \
   } while (0)
 
-  // FP64 with alpha = +-1: the accumulators start at Cin / alpha, so the Cin
-  // loads overlap the first stage's loads instead of stalling the epilogue
+  // FP64 with alpha = +-1: the accumulators start at Cin / alpha, so the epilogue does not
+  // wait for Cin loads.  (Issuing the first stage's operand loads before them would overlap the
+  // two, but with both live the 128 x 128 kernels spill.)
   const bool c_pre = CT<R>::exact && g.c_kind != SRC_NONE && (g.alpha == 1.0 || g.alpha == -1.0);
   const int64_t c_off = form_group_off(g.Cf, b);
   const int r_w = row0 + wm * WTM, c_w = col0 + wn * WTN + (lane & 15);
@@ -304,14 +305,31 @@ __global__ __launch_bounds__(64 * WGM * WGN, (!CT<R>::exact && AK == AK_MAT) ? 4
     for (int i = 0; i < FM; ++i) {
       int ro[4];
       c_src_rows<R>(g, b, r_w + 16 * i, lane, ro);
+      if (g.c_kind == SRC_MAT) {  // a whole block row's loads in flight at once
+        const z64* base = g.Cin.p + (int64_t)b * g.Cin.bstride;
+        z64 cv[FN][4];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        z64 cv[4];
-        c_quad<R>(g, b, r_w + 16 * i, c_w + 16 * j, lane, c_off, ro, cv);
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          accr[i][j][v] = (R)(g.alpha * cv[v].x);
-          acci[i][j][v] = (R)(g.alpha * cv[v].y);
+          for (int v = 0; v < 4; ++v) cv[j][v] = base[(int64_t)ro[v] * g.Cin.ld + c_w + 16 * j];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            accr[i][j][v] = (R)(g.alpha * cv[j][v].x);
+            acci[i][j][v] = (R)(g.alpha * cv[j][v].y);
+          }
+      } else {
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          z64 cv[4];
+          c_quad<R>(g, b, r_w + 16 * i, c_w + 16 * j, lane, c_off, ro, cv);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            accr[i][j][v] = (R)(g.alpha * cv[v].x);
+            acci[i][j][v] = (R)(g.alpha * cv[v].y);
+          }
         }
       }
     }

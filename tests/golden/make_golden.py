@@ -1,8 +1,9 @@
 """Write the oracle's expected values for sampled energies of the full-size workloads.
 
 Calls only ``oracle`` and ``synth`` (no GPU code).  Usage:
-    python tests/golden/make_golden.py [name ...]
-with names from c2 c3 c4 kmesh_m256 bias_m1024 kpm_m1024 (default: all).
+    python tests/golden/make_golden.py [--jobs N] [name ...]
+with names from c2 c3 c4 c4_bloch kmesh_m256 bias_m1024 kpm_m1024
+(default: all; c4_bloch reads c4.json).
 
 Transmission configs (tests/golden/<cfg>.json): grid indices, energies and
 the FP64 oracle's T_LR (block-Thomas solve, Sancho-Rubio leads), the
@@ -12,6 +13,13 @@ imaginary part of the trace and the decimation iteration counts.
         extrema (bands on 512 k-points);
   c4 -- 8 seeded grid points plus the 8 nearest the band extrema (bands on
         256 k-points); about 3 CPU-minutes per energy on 8 cores.
+  c4_bloch -- add to c4.json, for every sampled energy, T from the
+        Bloch-mode construction of the lead surface GFs (``method="bloch"``,
+        an algorithm independent of decimation) on the same block-Thomas
+        solve.  Where the lead's bands have sharp features T's FP64 value is
+        only reproducible to the spread of such constructions (the tests add
+        it to the bar).  One 2M x 2M eigenproblem per energy, about 14 CPU-
+        minutes at M = 1024; --jobs N runs N energies at once.
 The forms beyond T(E) at the shapes the benchmark times, reduced in the
 layer count only:
   kmesh_m256 -- the benchmark's k-mesh recipe (decay-weighted layers of
@@ -50,17 +58,52 @@ BIAS = {"N": 3, "V": 0.2, "energies": [-0.35, 0.02, 0.31]}
 KPM = {"N": 4, "R": 4, "n_mom": 48, "vector_seed": 2024}
 
 
-def sample_indices(cfg, n_rand: int, n_edge: int, nk: int, seed: int) -> np.ndarray:
+def sample_indices(cfg, n_rand: int, n_edge: int, nk: int, seed: int, edges_only: bool = False) -> np.ndarray:
+    """Seeded grid points plus the n_edge grid points nearest the lead's band extrema (those not
+    already drawn); edges_only returns the latter alone."""
     rng = np.random.default_rng(np.random.SeedSequence([seed, 0, 7]))
     idx = set(rng.choice(len(cfg.energies), size=n_rand, replace=False).tolist())
+    edge = []
     if n_edge:
         ext = oracle.band_extrema(cfg.device.left, nk=nk)
         dist = np.min(np.abs(cfg.energies[:, None] - ext[None, :]), axis=1)
         for i in np.argsort(dist, kind="stable"):
             if len(idx) >= n_rand + n_edge:
                 break
-            idx.add(int(i))
-    return np.array(sorted(idx))
+            if int(i) not in idx:
+                idx.add(int(i))
+                edge.append(int(i))
+    return np.array(sorted(edge if edges_only else idx))
+
+
+def _bloch_T(args):
+    name, i = args
+    from threadpoolctl import threadpool_limits
+    cfg = CONFIGS[name]()
+    z = complex(cfg.energies[i], cfg.eta)
+    with threadpool_limits(limits=2):
+        sl, sr, _ = oracle.self_energies(cfg.device.left, cfg.device.right, z, method="bloch")
+        return i, float(oracle.transmission_block_thomas(cfg.device, z, sl, sr).real)
+
+
+def bloch_spread(name, jobs):
+    """T from Bloch-mode leads at every sampled energy of an existing golden (see the header);
+    also records which samples are the band-edge picks."""
+    import concurrent.futures as cf
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path) as f:
+        out = json.load(f)
+    cfg = CONFIGS[name]()
+    edge = sample_indices(cfg, *SAMPLES[name], seed=SEEDS[name], edges_only=True).tolist()
+    assert all(i in out["indices"] for i in edge)
+    t0 = time.time()
+    with cf.ProcessPoolExecutor(max_workers=jobs) as ex:
+        res = dict(ex.map(_bloch_T, [(name, i) for i in out["indices"]]))
+    out["edge_indices"] = edge
+    out["T_bloch"] = [res[i] for i in out["indices"]]
+    out["bloch_oracle"] = "oracle.self_energies(method='bloch') + oracle.transmission_block_thomas, FP64"
+    out["bloch_cpu_seconds"] = round(time.time() - t0, 1)
+    write(name, out)
 
 
 def write(name, out):
@@ -70,13 +113,17 @@ def write(name, out):
     print(f"{name}: {out.get('cpu_seconds')} s -> {path}", flush=True)
 
 
+CONFIGS = {"c2": synth.config_c2, "c3": synth.config_c3, "c4": synth.config_c4}
+SEEDS = {"c2": 2, "c3": 3, "c4": 4}
+
+
 def transmission_config(name):
-    cfg = {"c2": synth.config_c2, "c3": synth.config_c3, "c4": synth.config_c4}[name]()
+    cfg = CONFIGS[name]()
     spec = SAMPLES[name]
     if spec is None:
         idx = np.arange(len(cfg.energies))
     else:
-        idx = sample_indices(cfg, *spec, seed={"c2": 2, "c3": 3, "c4": 4}[name])
+        idx = sample_indices(cfg, *spec, seed=SEEDS[name])
     E = cfg.energies[idx]
     t0 = time.time()
     T, tr, infos = oracle.transmission(cfg.device, E, cfg.eta, method="thomas", return_info=True)
@@ -114,11 +161,13 @@ def kpm_device():
     return sub, lo, hi, r
 
 
-def main(names):
+def main(names, jobs=1):
     for name in names:
         t0 = time.time()
         if name in SAMPLES:
             transmission_config(name)
+        elif name.endswith("_bloch") and name[:-6] in SAMPLES:
+            bloch_spread(name[:-6], jobs)
         elif name == "kmesh_m256":
             cfg, images, R, kk, w, E = kmesh_device()
             T, Tk = okm.transmission_kmesh(images, R, kk, w, E, cfg.eta, method="thomas")
@@ -144,4 +193,10 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["kpm_m1024", "bias_m1024", "kmesh_m256", "c2", "c3", "c4"])
+    argv = sys.argv[1:]
+    jobs = 1
+    if "--jobs" in argv:
+        k = argv.index("--jobs")
+        jobs = int(argv[k + 1])
+        del argv[k:k + 2]
+    main(argv or ["kpm_m1024", "bias_m1024", "kmesh_m256", "c2", "c3", "c4", "c4_bloch"], jobs)

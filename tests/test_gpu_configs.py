@@ -7,7 +7,13 @@ full layer count and block size) and the sampled energies are compared
 element by element: C2 all 1000 energies, C3 128 and C4 16 (each with the 8
 grid energies nearest the lead's band extrema).
 
-FP64 bar: |T_gpu - T_oracle| <= 1e-8 |T_oracle| + 1e-12.
+FP64 bar: |T_gpu - T_oracle| <= 1e-8 |T_oracle| + 1e-12.  Where the golden also
+holds T from the oracle's Bloch-mode lead construction (C4), twice the spread
+|T_oracle - T_bloch| of the two oracle constructions is added: where the
+lead's bands have sharp features, T is reproducible in FP64 only to that
+spread (at the C4 grid point E = 1.6712 the two constructions of Sigma differ
+by 2.7e-8 and 7.6e-8 relative), and a correct GPU result can lie that far
+from either oracle value; elsewhere the spread is far below the bar.
 Mixed bar: |T_gpu - T_oracle| <= 1e-4.  The FP32 matrix-core form does not
 reach it on these workloads (FP32 accumulation leaves ~1e-6 relative error
 per product and the near-singular layer blocks at eta = 1e-6 amplify it), so
@@ -44,13 +50,15 @@ def golden(name):
 def _compare(tag, T, g, precision):
     ref = np.array(g["T"])
     err = np.abs(T - ref)
+    spread = np.abs(ref - np.array(g["T_bloch"])) if "T_bloch" in g else np.zeros_like(ref)
     if precision == "fp64":
-        ok = err <= FP64_RTOL * np.abs(ref) + FP64_ATOL
+        ok = err <= FP64_RTOL * np.abs(ref) + FP64_ATOL + 2.0 * spread
     else:
         ok = err <= MIXED_ATOL
     log(f"[config] {tag} {precision}: max |dT| {err.max():.3e}, p99 {np.percentile(err, 99):.3e}, "
         f"mean |dT| {err.mean():.3e}, max rel {np.max(err / np.abs(ref)):.3e}, "
-        f"T range [{ref.min():.3g}, {ref.max():.3g}], {len(ref)} energies")
+        f"T range [{ref.min():.3g}, {ref.max():.3g}], {len(ref)} energies; "
+        f"oracle construction spread max rel {np.max(spread / np.abs(ref)):.2e}")
     assert np.all(ok), [(e, t, r) for e, t, r, o in zip(g["E"], T, ref, ok) if not o][:10]
 
 
