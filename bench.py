@@ -508,13 +508,17 @@ def run_kernel_timing(args) -> int:
         print(line + f" rc={rc}", flush=True)
     if args.only_product:
         return 0
+    lib.rgf_ktest_set_lookahead.argtypes = [C.c_int]
     for Mp in (256, 512, 1024):
         for k in ((small_k, 0) if small_k else (0,)):
-            lib.rgf_ktest_set_small_k(k)
-            rc = lib.rgf_ktest_lu_time(prec, Mp, Mp, 64, 3, C.byref(f), C.byref(sv))
-            print(f"LU Mp={Mp}, 64 energies, short-K tiles up to K = {k}: factor {f.value:.2f} ms, "
-                  f"solves {sv.value:.2f} ms rc={rc}", flush=True)
+            for la in (1, 0):
+                lib.rgf_ktest_set_small_k(k)
+                lib.rgf_ktest_set_lookahead(la)
+                rc = lib.rgf_ktest_lu_time(prec, Mp, Mp, 64, 3, C.byref(f), C.byref(sv))
+                print(f"LU Mp={Mp}, 64 energies, short-K tiles up to K = {k}, look-ahead {la}: "
+                      f"factor {f.value:.2f} ms, solves {sv.value:.2f} ms rc={rc}", flush=True)
         lib.rgf_ktest_set_small_k(small_k)
+        lib.rgf_ktest_set_lookahead(1)
     return 0
 
 

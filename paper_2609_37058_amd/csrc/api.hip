@@ -477,7 +477,7 @@ static void sweep_graph(Engine& eng, const rgf_device& d, bool same, double eta,
 // ls, in the arena `base` laid out as `lay` (lay.batch == B).
 static void run_chunk(const rgf_device& d, const double* E, int64_t e0, int B, double eta, int precision,
                       double* T, int32_t* info, char* base, const Layout& lay, int32_t* host_active, bool graphs,
-                      hipStream_t ls, double u_l, double u_r, const Grouping& grp) {
+                      hipStream_t ls, double u_l, double u_r, const Grouping& grp, bool lookahead = true) {
   // one decimation serves both sides only for the same electrode at the same shift
   const bool same = same_lead(d.left, d.right) && u_l == u_r;
   const bool biased = u_l != 0.0 || u_r != 0.0;
@@ -489,6 +489,7 @@ static void run_chunk(const rgf_device& d, const double* E, int64_t e0, int B, d
     Ec = Ew;
   }
   Engine eng(base, lay, ls, prec, d.M, Ec, eta, host_active);
+  eng.set_lookahead(lookahead);
   if (grp.per > 0) eng.set_group(grp.per, e0, grp.stride);
   if (biased) {  // a rigidly shifted electrode is the unshifted one at E - u
     double* El = reinterpret_cast<double*>(base + lay.elead);
@@ -580,8 +581,9 @@ static void transmission_noalloc_impl(const rgf_device& d, const double* E, int6
   std::lock_guard<std::mutex> call(stream_call_mutex(dev, st));
   for (int64_t e0 = 0; e0 < nE;) {
     const int B = (int)std::min<int64_t>(chunk, nE - e0);
+    // no look-ahead in the blocked LU: its side stream would be created on first use
     run_chunk(d, E, e0, B, eta, precision, T, info, base, Layout::make(Mp, B), &g_scratch_active[dev], false, st,
-              0.0, 0.0, Grouping());
+              0.0, 0.0, Grouping(), false);
     e0 += B;
   }
 }

@@ -30,7 +30,7 @@ struct Layout {
   int nblk_sr = 0;
   size_t bytes = 0;
   // offsets (bytes) into the arena
-  size_t sig, un, linv, uinv, perm, cand, flags, ints, dbl;
+  size_t sig, un, linv, uinv, perm, cand, cand2, flags, ints, dbl;
   size_t energies, tout, iout;  // staged energies and sweep outputs (stable addresses for graphs)
   size_t elead, erlead;         // energies of the left / right electrode when biased (E - u)
   static Layout make(int Mp, int batch);
@@ -50,6 +50,11 @@ class Engine {
   // A grouped batch: entry b uses the device and electrode blocks of group
   // (b0 + b) / per, `stride` elements after those of the group before; the
   // blocks passed to the calls below are those of group 0.
+  // Look-ahead in the blocked LU (a side stream per stream, created on first use; on with
+  // RGF_LOOKAHEAD=1).  Callers that must not create streams turn it off.
+  void set_lookahead(bool on) {
+    if (!on) lu_.cand2 = nullptr;
+  }
   void set_group(int per, int64_t b0, int64_t stride) {
     gper_ = per;
     gb0_ = b0;
@@ -117,6 +122,7 @@ class Engine {
   z64 *eps_, *epsL_, *epsR_, *AB_, *C_, *Tsr_, *Ysr_;
   z64 *T_, *Y_, *Wa_, *Wb_, *P_, *Z1_, *Z2_;
   LuBufs lu_;
+  int32_t* cand2_ = nullptr;
   int32_t *done_l_, *done_r_, *iters_, *sing_, *active_;
   double *scale_, *partial_;
   int32_t* host_active_;

@@ -55,6 +55,7 @@ Layout Layout::make(int Mp, int batch) {
   l.uinv = take((size_t)batch * 64 * Mp * Z);
   l.perm = take((size_t)batch * Mp * 4);
   l.cand = take((size_t)batch * Mp * 4);
+  l.cand2 = take((size_t)batch * Mp * 4);
   l.flags = take((size_t)batch * Mp);
   l.ints = take((size_t)(4 * batch + 64) * 4);
   l.dbl = take((size_t)(batch + batch * l.nblk_sr * 2) * 8);
@@ -73,6 +74,14 @@ Layout Layout::make(int Mp, int batch) {
 // where its K = 16 updates make it HBM-bound.  RGF_FUSED=0 in the environment selects the
 // batched LU everywhere.
 constexpr int FUSED_MAX_MP = 192;
+// Look-ahead in the blocked LU (lu_factor) is opt-in: RGF_LOOKAHEAD=1 in the environment.
+// Measured at Mp = 1024, 64 energies: the factorisation alone 9.67 -> 8.64 ms and a one-lane
+// sweep +4.9%, but the default two-lane C4 run 1353 -> 1251 point-layers/s (each lane's side
+// stream adds to the streams sharing the device's hardware queues).
+static bool lookahead_default() {
+  const char* s = std::getenv("RGF_LOOKAHEAD");
+  return s && std::atoi(s) == 1;
+}
 static bool fused_for(int Mp) {
   if (Mp > FUSED_MAX_MP) return false;
   const char* s = std::getenv("RGF_FUSED");
@@ -112,6 +121,8 @@ Engine::Engine(char* arena, const Layout& lay, hipStream_t st, int prec, int M, 
   lu_.uinv = reinterpret_cast<z64*>(arena + lay.uinv);
   lu_.perm = reinterpret_cast<int32_t*>(arena + lay.perm);
   lu_.cand = reinterpret_cast<int32_t*>(arena + lay.cand);
+  cand2_ = reinterpret_cast<int32_t*>(arena + lay.cand2);
+  lu_.cand2 = lookahead_default() ? cand2_ : nullptr;
   lu_.flags = reinterpret_cast<uint8_t*>(arena + lay.flags);
   int32_t* ints = reinterpret_cast<int32_t*>(arena + lay.ints);
   done_l_ = ints;

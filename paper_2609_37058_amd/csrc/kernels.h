@@ -143,6 +143,8 @@ struct LuPanelArgs {
 void launch_lu_panel(const LuPanelArgs& a, int batch, hipStream_t st);
 
 // Buffers of a batched LU (per batch: linv, uinv 64 x Mp each, perm, cand Mp, flags Mp, sing 1).
+// cand2 (Mp per batch, optional) is a second candidate list: with it the factorisation looks
+// ahead (see lu_factor), alternating the two lists between pairs of panels.
 struct LuBufs {
   z64* linv;
   z64* uinv;
@@ -150,9 +152,13 @@ struct LuBufs {
   int32_t* cand;
   uint8_t* flags;
   int32_t* sing;
+  int32_t* cand2 = nullptr;
 };
 // Factor T (Mp x Mp per batch, batch stride bs) in place.  Block products
 // (trailing updates) run in `prec`; pivoting and diagonal blocks in FP64.
+// With g.cand2 set (and st not capturing a graph), the columns more than one
+// pair of panels ahead are updated on a side stream while st factors the next
+// pair; st has waited for all of it when the call returns.
 void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int32_t* skip, int32_t code,
                int prec, int tile, hipStream_t st);
 // Y <- U^-1 L^-1 Y in place (Y = P RHS already gathered; Mp x nrhs per batch, ld nrhs).

@@ -16,11 +16,38 @@
 // with L[k, :] = B[perm[k-block], :] (multipliers) and U likewise; the
 // 128 x 128 diagonal triangle is applied as two 64-row inverse blocks and one
 // 64-row coupling product.
+#include <map>
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace rgf {
 
+
+// The side stream of a look-ahead factorisation on stream `st` (created once per device and
+// stream, default priority), with its fork and join events; null while st captures a graph.
+struct SideStream {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, far = nullptr;
+};
+static SideStream* side_stream(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  RGF_HIP(hipStreamIsCapturing(st, &cs));
+  if (cs != hipStreamCaptureStatusNone) return nullptr;
+  int dev = 0;
+  RGF_HIP(hipGetDevice(&dev));
+  static std::mutex mu;
+  static std::map<std::pair<int, hipStream_t>, SideStream> sides;
+  std::lock_guard<std::mutex> lk(mu);
+  SideStream& s = sides[{dev, st}];
+  if (!s.st) {
+    RGF_HIP(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
+    RGF_HIP(hipEventCreateWithFlags(&s.fork, hipEventDisableTiming));
+    RGF_HIP(hipEventCreateWithFlags(&s.far, hipEventDisableTiming));
+  }
+  return &s;
+}
 
 void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int32_t* skip, int32_t code,
                int prec, int tile, hipStream_t st) {
@@ -35,7 +62,8 @@ void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int
     f.ctl.skip = skip;
     launch_fill(f, batch, st);
   }
-  auto panel = [&](int k0) {
+  // the panel kernel writes the list of rows still candidates into `cand`
+  auto panel = [&](int k0, int32_t* cand) {
     LuPanelArgs pa;
     pa.T = mat(T, bs, Mp);
     pa.Mp = Mp;
@@ -47,7 +75,7 @@ void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int
     pa.perm_bs = Mp;
     pa.flags = g.flags;
     pa.flags_bs = Mp;
-    pa.cand = g.cand;
+    pa.cand = cand;
     pa.cand_bs = Mp;
     pa.sing = g.sing;
     pa.sing_code = code;
@@ -55,15 +83,15 @@ void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int
     launch_lu_panel(pa, batch, st);
   };
   // B[piv(k0), c0 : c0 + ncols] = L11(k0)^-1 B[piv(k0), ...], in place (one row tile)
-  auto u12 = [&](int k0, int c0, int ncols) {
+  auto u12 = [&](int k0, int c0, int ncols, hipStream_t s) {
     GemmArgs u = gemm_args(LU_NB, ncols, LU_NB, batch, skip);
     u.A = mat(g.linv + (int64_t)(k0 / LU_NB) * 64 * 64, inv_bs, 64);
     u.B = mat(T + c0, bs, Mp, g.perm + k0, Mp);
     u.C = u.B;
-    launch_gemm(u, prec, tile, st, 0);
+    launch_gemm(u, prec, tile, s, 0);
   };
   // B[rows, c0 : c0 + ncols] -= B[rows, k0 : k0 + K] B[piv(k0 .. k0 + K), c0 : ...]
-  auto update = [&](const int32_t* rows, int nrows, int k0, int K, int c0, int ncols) {
+  auto update = [&](const int32_t* rows, int nrows, int k0, int K, int c0, int ncols, hipStream_t s) {
     GemmArgs t = gemm_args(nrows, ncols, K, batch, skip);
     t.A = mat(T + k0, bs, Mp, rows, Mp);
     t.B = mat(T + c0, bs, Mp, g.perm + k0, Mp);
@@ -71,26 +99,55 @@ void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int
     t.Cin = mat(T + c0, bs, Mp, rows, Mp);
     t.C = t.Cin;
     t.alpha = -1.0;
-    launch_gemm(t, prec, tile, st, 0);
+    launch_gemm(t, prec, tile, s, 0);
   };
   // Panels in pairs (k0, k0 + 64): the second panel's columns are updated by the first
   // alone, then the columns right of the pair by both at once (inner dimension 128),
   // which halves the trailing updates and their C traffic.
-  int k0 = 0;
-  for (; k0 + 2 * LU_NB <= Mp; k0 += 2 * LU_NB) {
+  //   Look-ahead: of the columns right of a pair, the next pair's 128 ("near") are updated on
+  // st and the rest ("far") on the side stream, so the next pair's panels -- one latency-bound
+  // workgroup per energy -- run beside the large far update instead of after it.  The far
+  // update reads only this pair's multipliers, pivots and candidate list and writes only far
+  // columns; the next pair touches only its near columns until it waits for the far update
+  // (its own right-hand columns are this pair's far ones).  The candidate lists of consecutive
+  // pairs alternate between cand and cand2, since the far update still reads this pair's list
+  // while the next pair's panels write theirs.
+  SideStream* side = g.cand2 ? side_stream(st) : nullptr;
+  bool far_pending = false;
+  auto join = [&]() {
+    if (far_pending) RGF_HIP(hipStreamWaitEvent(st, side->far, 0));
+    far_pending = false;
+  };
+  auto rest_ops = [&](int k0, int32_t* cand, int rest, int c, int ncols, hipStream_t s) {
+    const int kb = k0 + LU_NB;
+    u12(k0, c, ncols, s);
+    update(g.perm + kb, LU_NB, k0, LU_NB, c, ncols, s);  // the second panel's pivot rows
+    u12(kb, c, ncols, s);
+    update(cand, rest, k0, 2 * LU_NB, c, ncols, s);      // candidates of the second panel
+  };
+  int k0 = 0, pair = 0;
+  for (; k0 + 2 * LU_NB <= Mp; k0 += 2 * LU_NB, ++pair) {
     const int kb = k0 + LU_NB, c0 = k0 + 2 * LU_NB;
     const int rest = Mp - c0;
-    panel(k0);
-    u12(k0, kb, LU_NB);
-    update(g.cand, Mp - kb, k0, LU_NB, kb, LU_NB);  // candidates of the first panel
-    panel(kb);
+    int32_t* cand = (side && (pair & 1)) ? g.cand2 : g.cand;
+    panel(k0, cand);
+    u12(k0, kb, LU_NB, st);
+    update(cand, Mp - kb, k0, LU_NB, kb, LU_NB, st);  // candidates of the first panel
+    panel(kb, cand);
     if (rest <= 0) continue;
-    u12(k0, c0, rest);
-    update(g.perm + kb, LU_NB, k0, LU_NB, c0, rest);  // the second panel's pivot rows
-    u12(kb, c0, rest);
-    update(g.cand, rest, k0, 2 * LU_NB, c0, rest);    // candidates of the second panel
+    join();  // this pair's right-hand columns were the previous pair's far ones
+    const int near = side ? std::min(rest, 2 * LU_NB) : rest;
+    rest_ops(k0, cand, rest, c0, near, st);
+    if (rest > near) {
+      RGF_HIP(hipEventRecord(side->fork, st));
+      RGF_HIP(hipStreamWaitEvent(side->st, side->fork, 0));
+      rest_ops(k0, cand, rest, c0 + near, rest - near, side->st);
+      RGF_HIP(hipEventRecord(side->far, side->st));
+      far_pending = true;
+    }
   }
-  if (k0 < Mp) panel(k0);  // an odd panel count ends on a single panel
+  join();
+  if (k0 < Mp) panel(k0, (side && (pair & 1)) ? g.cand2 : g.cand);  // an odd panel count ends on a single panel
 }
 
 // Y_rows = Y_rows - A_rows Y_src  (rows x nrhs, inner dimension K)

@@ -20,7 +20,17 @@ static int kt_guard(F&& f) {
   }
 }
 
+// Whether the harness's LU runs look ahead (a second candidate list, see lu_factor).
+static int g_kt_lookahead = 1;
+
 extern "C" {
+
+// Turn the look-ahead of the harness's LU on (1) or off (0); returns the previous setting.
+int rgf_ktest_set_lookahead(int on) {
+  const int prev = g_kt_lookahead;
+  g_kt_lookahead = on ? 1 : 0;
+  return prev;
+}
 
 // C[b] = alpha * A[b] B[b] (+ C[b] when accumulate), dense row-major, device pointers.
 int rgf_ktest_gemm(int prec, int tile, int rows, int cols, int K, int batch, const void* A, const void* B,
@@ -56,6 +66,7 @@ int rgf_ktest_lu(int prec, int Mp, int nrhs, int batch, void* B, const void* RHS
     RGF_HIP(hipMalloc((void**)&g.uinv, sizeof(z64) * batch * 64 * Mp));
     RGF_HIP(hipMalloc((void**)&g.perm, sizeof(int32_t) * batch * Mp));
     RGF_HIP(hipMalloc((void**)&g.cand, sizeof(int32_t) * batch * Mp));
+    if (g_kt_lookahead) RGF_HIP(hipMalloc((void**)&g.cand2, sizeof(int32_t) * batch * Mp));
     RGF_HIP(hipMalloc((void**)&g.flags, batch * Mp));
     RGF_HIP(hipMalloc((void**)&g.sing, sizeof(int32_t) * batch));
     RGF_HIP(hipMemset(g.sing, 0, sizeof(int32_t) * batch));
@@ -84,6 +95,7 @@ int rgf_ktest_lu(int prec, int Mp, int nrhs, int batch, void* B, const void* RHS
     RGF_HIP(hipFree(g.uinv));
     RGF_HIP(hipFree(g.perm));
     RGF_HIP(hipFree(g.cand));
+    if (g.cand2) RGF_HIP(hipFree(g.cand2));
     RGF_HIP(hipFree(g.flags));
     RGF_HIP(hipFree(g.sing));
   });
@@ -219,6 +231,7 @@ int rgf_ktest_lu_time(int prec, int Mp, int nrhs, int batch, int reps, double* m
     RGF_HIP(hipMalloc((void**)&g.uinv, sizeof(z64) * batch * 64 * Mp));
     RGF_HIP(hipMalloc((void**)&g.perm, sizeof(int32_t) * batch * Mp));
     RGF_HIP(hipMalloc((void**)&g.cand, sizeof(int32_t) * batch * Mp));
+    if (g_kt_lookahead) RGF_HIP(hipMalloc((void**)&g.cand2, sizeof(int32_t) * batch * Mp));
     RGF_HIP(hipMalloc((void**)&g.flags, batch * Mp));
     RGF_HIP(hipMalloc((void**)&g.sing, sizeof(int32_t) * batch));
     RGF_HIP(hipMalloc((void**)&B0, sizeof(z64) * batch * bs));
@@ -252,6 +265,7 @@ int rgf_ktest_lu_time(int prec, int Mp, int nrhs, int batch, int reps, double* m
     for (void* q : {(void*)g.linv, (void*)g.uinv, (void*)g.perm, (void*)g.cand, (void*)g.flags, (void*)g.sing,
                     (void*)B0, (void*)B, (void*)Y})
       RGF_HIP(hipFree(q));
+    if (g.cand2) RGF_HIP(hipFree(g.cand2));
   });
 }
 

@@ -32,6 +32,7 @@ def kt():
     lib.rgf_ktest_form_ct.argtypes = [C.c_int] * 5 + [C.c_void_p] * 3 + [C.c_double, C.c_void_p, C.c_void_p]
     lib.rgf_ktest_gj.argtypes = [C.c_int] * 3 + [C.c_void_p] * 6
     lib.rgf_ktest_set_small_k.argtypes = [C.c_int]
+    lib.rgf_ktest_set_lookahead.argtypes = [C.c_int]
     return lib
 
 
@@ -90,6 +91,40 @@ def test_short_k_tiles_bitwise_equal_to_wide_tiles(kt, prec, rows, cols, K, batc
     assert np.array_equal(out[0], out[1])
     ref = C0 - A @ B
     assert np.max(np.abs(out[0] - ref)) / np.max(np.abs(ref)) < (1e-14 if prec == 0 else 2e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("Mp,batch", [(320, 3), (512, 2), (1024, 2), (1152, 2)])
+def test_lu_lookahead_bitwise_equal(kt, prec, Mp, batch):
+    """The look-ahead factorisation (far columns updated on a side stream, candidate lists
+    alternating between pairs of panels) runs the same products on the same data as the plain
+    one, split at other column boundaries: identical bits, and the solve still matches numpy."""
+    import torch
+    rng = np.random.default_rng(Mp + 3 * batch)
+    Bm = _rand(rng, (batch, Mp, Mp)) * np.exp(rng.uniform(-3, 3, size=(batch, Mp, 1)))
+    R = _rand(rng, (batch, Mp, 64))
+    tr = torch.as_tensor(np.ascontiguousarray(R)).cuda()
+    outs = []
+    prev = kt.rgf_ktest_set_lookahead(1)
+    try:
+        for la in (1, 0):
+            kt.rgf_ktest_set_lookahead(la)
+            tb = torch.as_tensor(np.ascontiguousarray(Bm)).cuda()
+            X = torch.zeros((batch, Mp, 64), dtype=torch.complex128, device="cuda")
+            perm = np.zeros((batch, Mp), np.int32)
+            sing = np.zeros(batch, np.int32)
+            log(f"[kernel] lu look-ahead={la} prec={prec} Mp={Mp} b={batch}")
+            assert kt.rgf_ktest_lu(prec, Mp, 64, batch, tb.data_ptr(), tr.data_ptr(), X.data_ptr(),
+                                   perm.ctypes.data, sing.ctypes.data) == 0
+            outs.append((X.cpu().numpy(), perm.copy(), sing.copy()))
+    finally:
+        kt.rgf_ktest_set_lookahead(prev)
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert np.all(outs[0][2] == 0)
+    ref = np.linalg.solve(Bm, R)
+    err = np.max(np.abs(outs[0][0] - ref)) / np.max(np.abs(ref))
+    # the bar of test_lu_solve_matches_numpy_solve (FP32: the error grows with the order)
+    assert err < (1e-11 if prec == 0 else 1e-3 * max(1.0, Mp / 512))
 
 
 @pytest.mark.parametrize("prec", [0, 1])

@@ -147,3 +147,22 @@ def test_empty_energy_grid(lib):
     T, info = lib.transmission(dt, torch.empty(0, dtype=torch.float64, device="cuda"), 1e-6)
     torch.cuda.synchronize()
     assert T.numel() == 0 and info.numel() == 0
+
+
+@pytest.mark.parametrize("M,lanes", [(300, "1"), (520, "2")])
+def test_lu_lookahead_equals_plain(lib, M, lanes, monkeypatch):
+    """RGF_LOOKAHEAD=1: the blocked LU updates the columns beyond the next pair of panels on a
+    side stream (per lane) while the lane factors that pair; the results are the same bits as
+    without it, and match the oracle."""
+    dev = synth.random_small_device(3, M, seed=500 + M)
+    E = np.linspace(-1.0, 1.0, 8)
+    st = stage(dev)
+    monkeypatch.setenv("RGF_LANES", lanes)
+    plain, info0 = gpu_transmission(st, E, 1e-6)
+    monkeypatch.setenv("RGF_LOOKAHEAD", "1")
+    log(f"[parity] look-ahead M={M} lanes={lanes}")
+    ahead, info1 = gpu_transmission(st, E, 1e-6)
+    assert np.all(info0 == 0) and np.all(info1 == 0)
+    assert np.array_equal(plain, ahead)
+    ok, rel, ab = fp64_close(ahead[:3], oracle.transmission(dev, E[:3], 1e-6))
+    assert ok, rel
