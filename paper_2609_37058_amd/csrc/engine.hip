@@ -76,8 +76,8 @@ Layout Layout::make(int Mp, int batch) {
 constexpr int FUSED_MAX_MP = 192;
 // Look-ahead in the blocked LU (lu_factor) is opt-in: RGF_LOOKAHEAD=1 in the environment.
 // Measured at Mp = 1024, 64 energies: the factorisation alone 9.67 -> 8.64 ms and a one-lane
-// sweep +4.9%, but the default two-lane C4 run 1353 -> 1251 point-layers/s (each lane's side
-// stream adds to the streams sharing the device's hardware queues).
+// sweep +4.9%, but the default two-lane C4 run 1353 -> 1251 point-layers/s (there one lane's
+// panels already overlap the other's products).
 static bool lookahead_default() {
   const char* s = std::getenv("RGF_LOOKAHEAD");
   return s && std::atoi(s) == 1;
