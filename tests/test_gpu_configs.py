@@ -5,7 +5,7 @@ tests/golden/make_golden.py, which calls only the FP64 oracle.  The GPU runs
 each workload in the configuration the benchmark times (whole energy batches,
 full layer count and block size) and the sampled energies are compared
 element by element: C2 all 1000 energies, C3 128 and C4 16 (each with the 8
-grid energies nearest the lead's band extrema).
+grid energies nearest the lead's band extrema); C4 runs in the benchmark's 256-energy step.
 
 FP64 bar: |T_gpu - T_oracle| <= 1e-8 |T_oracle| + 1e-12.  Where the golden also
 holds T from the oracle's Bloch-mode lead construction (C4), twice the spread
@@ -108,12 +108,12 @@ def c4_dev():
 
 @_precision_param()
 def test_c4_sampled(lib, c4_dev, precision):
-    """400 layers, M = 1024 (25 GiB of blocks): the 16 sampled energies inside a 64-energy batch
-    (the benchmark's lane chunk)."""
+    """400 layers, M = 1024 (25 GiB of blocks): the 16 sampled energies inside a 256-energy call,
+    the benchmark's step (two lanes of 128)."""
     cfg, dt = c4_dev
     g = golden("c4")
     idx = np.array(g["indices"])
-    batch = np.concatenate([cfg.energies[idx], cfg.energies[100:100 + 64 - len(idx)]])
+    batch = np.concatenate([cfg.energies[idx], cfg.energies[100:100 + 256 - len(idx)]])
     log(f"[config] c4 {precision}: N={cfg.device.N} M={cfg.device.M} batch={len(batch)}")
     T, info = gpu_transmission(dt, batch, cfg.eta, precision)
     assert np.all(info == 0)
