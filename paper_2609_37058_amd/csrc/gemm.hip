@@ -399,24 +399,28 @@ __global__ __launch_bounds__(64 * WGM * WGN, (!CT<R>::exact && AK == AK_MAT) ? 4
         }
       }
     }
-  } else if (g.c_kind == SRC_MAT) {
-    // FP32 with a stored Cin (the LU updates and solves of the mixed form): one 16 x 16 block's
-    // loads at a time, within the 128-VGPR budget
+  } else if (g.c_kind != SRC_FORM) {
+    // FP32 with a stored Cin or none (the LU updates, U12 blocks and solves of the mixed form):
+    // the output rows' indices per block row and one 16 x 16 block's Cin loads at a time, within
+    // the 128-VGPR budget
+    const bool has_c = g.c_kind == SRC_MAT;
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
       int rs[4], ro[4];
-      frag_rows<R>(g.Cin, b, r_w + 16 * i, lane, rs);
+      if (has_c) frag_rows<R>(g.Cin, b, r_w + 16 * i, lane, rs);
       frag_rows<R>(g.C, b, r_w + 16 * i, lane, ro);
-      const z64* cin = g.Cin.p + (int64_t)b * g.Cin.bstride;
+      const z64* cin = has_c ? g.Cin.p + (int64_t)b * g.Cin.bstride : nullptr;
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         z64 cv[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) cv[v] = cin[(int64_t)rs[v] * g.Cin.ld + c_w + 16 * j];
+        for (int v = 0; v < 4; ++v)
+          if (has_c) cv[v] = cin[(int64_t)rs[v] * g.Cin.ld + c_w + 16 * j];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const z64 out = zmake(g.alpha * (double)accr[i][j][v] + cv[v].x, g.alpha * (double)acci[i][j][v] + cv[v].y);
+          z64 out = zmake(g.alpha * (double)accr[i][j][v], g.alpha * (double)acci[i][j][v]);
+          if (has_c) out = zadd(out, cv[v]);
           cbase[(int64_t)ro[v] * g.C.ld + c_w + 16 * j] = out;
         }
       }
