@@ -441,6 +441,25 @@ def class_rooflines(cls: dict, prec: str, mixed_parts: int = 7) -> dict:
     return out
 
 
+def isolated_sweep_launch_ms(Mp: int, batch: int, prec: int):
+    """Average duration (ms) of the sweep's two role-1 launch forms -- W' = -W X on stored operands,
+    B' = A - L X with L stored and A formed -- at the step's shape, each alone on the device
+    (3 launches each after one untimed, HIP events), through the test-only harness librgf_ktest.so.
+    None when the harness is not built or a call fails."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_2609_37058_amd", "librgf_ktest.so")
+    if not os.path.exists(path):
+        return None
+    lib = C.CDLL(path)
+    lib.rgf_ktest_sweep_time.argtypes = [C.c_int] * 5 + [C.POINTER(C.c_double)]
+    ms, t = C.c_double(), []
+    for variant in (0, 2):
+        if lib.rgf_ktest_sweep_time(prec, variant, Mp, batch, 3, C.byref(ms)) != 0:
+            return None
+        t.append(ms.value)
+    return sum(t) / len(t)
+
+
 def run_kernel_timing(args) -> int:
     """Isolated timings of the block-product shapes of one C4 layer (Mp = 1024, 64 energies per
     launch), the skinny KPM products and the batched LU, through the test-only harness
@@ -715,6 +734,19 @@ def main():
         sr_ms = ev0.elapsed_time(ev1)
         out["parts_ms_per_step"] = {"self_energy_alone": sr_ms,
                                     "sweep_and_trace": results["fp64"]["ms_per_step"] - sr_ms}
+    if dom == "sweep" and sw["launches"] and left() > tail_s:
+        # The two energy lanes run their kernels at the same time, so a launch's event-timed
+        # duration above includes device time shared with the other lane's kernels.  The same
+        # launches alone on the device give the kernel's own rate.
+        per_launch = int(round(sw["flops"] / sw["launches"] / (8.0 * d_mp ** 3)))
+        iso = isolated_sweep_launch_ms(d_mp, per_launch, 0 if hp == "fp64" or not parts & 1 else 1)
+        if iso:
+            ach = 8.0 * d_mp ** 3 * per_launch / (iso / 1e3) / 1e12
+            out["roofline"]["isolated"] = {
+                "avg_launch_ms": iso, "achieved": ach, "frac": ach / out["roofline"]["peak"],
+                "energies_per_launch": per_launch,
+                "note": "the same two launch forms at the step's shape, each alone on the device after the "
+                        "timed region; the live figures above share the device with the other energy lane"}
     if "mixed" in results and "fp64" in results:
         m = results["mixed"]
         dts = [np.abs(T_by_step["mixed"][j] - T_by_step["fp64"][j]) for j in T_by_step["mixed"]

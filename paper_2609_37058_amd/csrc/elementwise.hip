@@ -12,31 +12,57 @@ namespace {
 
 constexpr int ET = 256;
 
-__global__ __launch_bounds__(ET) void fill_kernel(FillArgs a) {
-  const int b = blockIdx.y;
+// One wavefront per destination row (FILL_ROWS rows per workgroup), so row indices, row
+// gathers and block offsets are resolved once per row and the columns stream through; the
+// batch index varies fastest over the grid, so the workgroups of different energies that read
+// the same source rows of a shared block run together and find them in L2.
+constexpr int FILL_ROWS = ET / 64;
+
+__global__ __launch_bounds__(ET) void fill_kernel(FillArgs a, int batch, int groups) {
+  const int b = blockIdx.x % batch, grp = blockIdx.x / batch;
   if (a.ctl.skip && a.ctl.skip[b]) return;
-  const int64_t n = (int64_t)a.rows * a.cols;
-  const int64_t e = (int64_t)blockIdx.x * ET + threadIdx.x;
-  if (a.flags && e < a.flags_n) a.flags[(int64_t)b * a.flags_bs + e] = 0;
-  if (e >= n) return;
-  const int r = (int)(e / a.cols), c = (int)(e % a.cols);
+  if (a.flags)
+    for (int e = grp * ET + threadIdx.x; e < a.flags_n; e += groups * ET) a.flags[(int64_t)b * a.flags_bs + e] = 0;
+  const int r = grp * FILL_ROWS + threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (r >= a.rows) return;
   const int rs = a.ridx ? a.ridx[(int64_t)b * a.ridx_bs + r] : r;
-  z64 v;
-  switch (a.kind) {
-    case FILL_IDENTITY: v = zmake(rs == c ? a.scale : 0.0, 0.0); break;
-    case FILL_MAT: {
-      z64 s = a.src.p[mat_off(a.src, b, r, c)];
-      v = zmake(a.scale * s.x, a.scale * s.y);
-      break;
+  z64* dst = a.dst.p + mat_off(a.dst, b, r, 0);
+  const double sc = a.scale;
+  if (a.kind == FILL_MAT) {
+    const z64* src = a.src.p + mat_off(a.src, b, r, 0);
+#pragma unroll 4
+    for (int c = lane; c < a.cols; c += 64) {
+      const z64 s = src[c];
+      dst[c] = zmake(sc * s.x, sc * s.y);
     }
-    case FILL_FORM: {
-      z64 s = form_elem(a.f, b, rs, c);
-      v = zmake(a.scale * s.x, a.scale * s.y);
-      break;
+  } else if (a.kind == FILL_FORM && !a.f.conj_t && !a.f.sub.p) {  // z S - H read along rows
+    const FormRef& f = a.f;
+    const z64 z = zmake(f.E[b], f.eta);
+    const bool in = rs < f.M;
+    const int64_t o = form_group_off(f, b) + (int64_t)(in ? rs : 0) * f.M;
+    const z64 *S = f.S + o, *H = f.H + o;
+    const int cm = in ? min(a.cols, f.M) : 0;
+#pragma unroll 4
+    for (int c = lane; c < cm; c += 64) {
+      const z64 v = zform(z, S[c], H[c]);
+      dst[c] = zmake(sc * v.x, sc * v.y);
     }
-    default: v = zmake(0.0, 0.0);
+    for (int c = cm + lane; c < a.cols; c += 64) dst[c] = zmake((f.pad_identity && rs == c) ? sc : 0.0, 0.0);
+  } else {
+    for (int c = lane; c < a.cols; c += 64) {
+      z64 v;
+      switch (a.kind) {
+        case FILL_IDENTITY: v = zmake(rs == c ? sc : 0.0, 0.0); break;
+        case FILL_FORM: {
+          const z64 s = form_elem(a.f, b, rs, c);
+          v = zmake(sc * s.x, sc * s.y);
+          break;
+        }
+        default: v = zmake(0.0, 0.0);
+      }
+      dst[c] = v;
+    }
   }
-  a.dst.p[mat_off(a.dst, b, r, c)] = v;
 }
 
 // Stored adjoint operand: dst[b] = z_b S^+ - H^+ over the padded Mp x Mp block,
@@ -374,8 +400,12 @@ void launch_random(z64* p, int64_t n, int64_t ld, int64_t rows, double scale, do
 
 void launch_fill(const FillArgs& a, int batch, hipStream_t st) {
   if (batch <= 0) return;
-  const int64_t n = std::max<int64_t>((int64_t)a.rows * a.cols, a.flags ? a.flags_n : 0);
-  hipLaunchKernelGGL(fill_kernel, dim3(nblocks(n), batch), dim3(ET), 0, st, a);
+  const int64_t groups = std::max<int64_t>((a.rows + FILL_ROWS - 1) / FILL_ROWS,
+                                           a.flags ? ((int64_t)a.flags_n + ET - 1) / ET : 0);
+  if (groups <= 0) return;
+  if (groups * batch > INT32_MAX)
+    throw Error{RGF_EINVAL, "fill: grid of " + std::to_string(groups * batch) + " workgroups"};
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)(groups * batch)), dim3(ET), 0, st, a, batch, (int)groups);
   RGF_HIP(hipGetLastError());
 }
 
