@@ -47,12 +47,18 @@ def parse():
                     help="wall-clock budget of the whole run in seconds, from process start (c4 workload)")
     ap.add_argument("--timed-s", type=float, default=100.0,
                     help="upper bound on the FP64 timed region in seconds (the mixed pass gets half of it)")
-    ap.add_argument("--profile-every", type=int, default=7,
+    ap.add_argument("--profile-every", type=int, default=11,
                     help="c4: time every n-th launch of each kernel class (0: the sweep products only); "
-                         "timing every launch slows the C4 step by 0.65%%, every 7th by nothing measurable")
+                         "timing every launch slows the C4 step by 0.65%%, every 11th by nothing measurable. "
+                         "11 is prime to each class's launches per layer (2, 14, 16, 78), so every launch "
+                         "position within a layer is sampled equally often")
     ap.add_argument("--energies-per-step", type=int, default=0,
-                    help="energies per step (0: the workload's own: c4 256 = two lanes of 128, bias 128, "
-                         "ldos 64, kmesh 16 per k-point)")
+                    help="energies per step (0: the workload's own: c4 256, bias 128, ldos 64, kmesh 16 per "
+                         "k-point)")
+    ap.add_argument("--lanes", type=int, default=1,
+                    help="c4: energy lanes of the step (0: the library's default, two at this block size); "
+                         "one lane keeps each kernel launch alone on the device, so a launch's measured "
+                         "duration is its own")
     ap.add_argument("--layers", type=int, default=400, help="principal layers (400 = the full workload)")
     ap.add_argument("--block", type=int, default=1024, help="block size M (1024 = the full workload)")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
@@ -431,6 +437,11 @@ def class_rooflines(cls: dict, prec: str, mixed_parts: int = 7) -> dict:
                                     or (name == "row64" and mixed_parts & 6))
         peak = PEAKS["fp32" if fp32 else "fp64"]
         ach = c["timed_flops"] / (c["ms"] / 1e3) / 1e12 if c["ms"] > 0 and c["timed_flops"] > 0 else None
+        if name == "lead":
+            # a decimation launch counts every energy of its batch, but energies whose decimation
+            # has converged skip it in-kernel; the class total is corrected to the executed
+            # iterations, a single launch's executed flops are not known
+            ach = None
         out[name] = {
             "what": CLASS_NAMES[name],
             "share_of_kernel_time": c["ms"] / total_ms if total_ms > 0 else None,
@@ -438,6 +449,10 @@ def class_rooflines(cls: dict, prec: str, mixed_parts: int = 7) -> dict:
             "launches": c["launches"], "flops": c["flops"],
             "achieved_tflops": ach, "peak_tflops": peak, "frac": (ach / peak) if ach else None,
         }
+        if name == "lead":
+            out[name]["flops_note"] = ("executed: the decimation's launches count only the iterations each "
+                                       "energy ran; no per-launch rate (it depends on the energies still "
+                                       "iterating)")
     return out
 
 
@@ -573,12 +588,17 @@ def main():
     dev_t = staging.stage_repeated(b.H00, b.H01, b.S00, b.S01, d.N, d.shifts)
     E_all = torch.as_tensor(cfg.energies).cuda()
     nE = len(cfg.energies)
-    # 256 energies per step (two lanes of 128): 2.5% above 128 per step on this workload, and one
-    # step still fits the timed window
+    # 256 energies per step, one lane: 1.8% above two lanes of 64 on this workload, and one step
+    # still fits the timed window.  Two lanes of 128 run 1.9% faster still, but the lanes then run
+    # their layers in lockstep, so every launch shares the device with the other lane's twin and
+    # its measured duration is about twice its own.
     B = min(args.energies_per_step or 256, nE)
     if args.tile:
         rgf.set_tile("fp64", args.tile)
         rgf.set_tile("mixed", args.tile)
+    if args.lanes:
+        rgf.set_tuning(d.M, "fp64", 0, args.lanes)
+        rgf.set_tuning(d.M, "mixed", 0, args.lanes)
     torch.cuda.synchronize()
     deadline = START + args.budget_s
     left = lambda: deadline - time.perf_counter()
@@ -735,8 +755,8 @@ def main():
         out["parts_ms_per_step"] = {"self_energy_alone": sr_ms,
                                     "sweep_and_trace": results["fp64"]["ms_per_step"] - sr_ms}
     if dom == "sweep" and sw["launches"] and left() > tail_s:
-        # The two energy lanes run their kernels at the same time, so a launch's event-timed
-        # duration above includes device time shared with the other lane's kernels.  The same
+        # With several energy lanes their kernels run at the same time, so a launch's event-timed
+        # duration above includes device time shared with the other lanes' kernels.  The same
         # launches alone on the device give the kernel's own rate.
         per_launch = int(round(sw["flops"] / sw["launches"] / (8.0 * d_mp ** 3)))
         iso = isolated_sweep_launch_ms(d_mp, per_launch, 0 if hp == "fp64" or not parts & 1 else 1)
@@ -746,7 +766,7 @@ def main():
                 "avg_launch_ms": iso, "achieved": ach, "frac": ach / out["roofline"]["peak"],
                 "energies_per_launch": per_launch,
                 "note": "the same two launch forms at the step's shape, each alone on the device after the "
-                        "timed region; the live figures above share the device with the other energy lane"}
+                        "timed region (with several energy lanes the live figures share the device)"}
     if "mixed" in results and "fp64" in results:
         m = results["mixed"]
         dts = [np.abs(T_by_step["mixed"][j] - T_by_step["fp64"][j]) for j in T_by_step["mixed"]

@@ -87,6 +87,7 @@ static Profiler g_prof;
 static thread_local hipEvent_t t_pending_begin = nullptr;
 static thread_local int t_prof_site = PC_OTHER;
 static thread_local bool t_prof_lead = false;
+static thread_local double t_prof_flops = 0.0;  // flops counted by this thread's launches
 Profiler& profiler() { return g_prof; }
 bool profiling() { return g_prof.on; }
 ProfSite::ProfSite(int cls) : prev(t_prof_site) { t_prof_site = cls; }
@@ -100,6 +101,11 @@ int profile_class(int role, int rows) {
   return t_prof_site;
 }
 int profile_panel_class() { return t_prof_lead ? PC_LEAD : PC_PANEL; }
+double profile_thread_flops() { return t_prof_flops; }
+void profile_uncount_flops(int cls, double flops) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (g_prof.on) g_prof.cls[cls].flops_all -= flops;
+}
 void profile_launch_begin(hipStream_t st, int cls) {
   t_pending_begin = nullptr;
   if (!g_prof.on) return;
@@ -114,6 +120,7 @@ void profile_launch_end(hipStream_t st, int cls, double flops) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.cls[cls].flops_all += flops;
   ++g_prof.cls[cls].launches_all;
+  t_prof_flops += flops;
   if (!t_pending_begin) return;
   hipEvent_t e = g_prof.get();
   RGF_HIP(hipEventRecord(e, st));

@@ -205,7 +205,11 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
   launch_frob_scale(mref(eps_, Mp, MM_), M_, M_, scale_, B_, st_);
 
   const int maxit = sr_maxit();
+  const bool prof = profiling();
+  const double flops0 = prof ? profile_thread_flops() : 0.0;
+  int run = 0;  // iterations launched
   for (int it = 1; it <= maxit; ++it) {
+    run = it;
     // [Xa Xb] = eps^-1 [alpha beta]
     FillArgs c = fill_args(mref(Tsr_, Mp, MM_), Mp, Mp, FILL_MAT);
     c.src = mref(eps_, Mp, MM_);
@@ -244,6 +248,17 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
       RGF_HIP(hipStreamSynchronize(st_));
       if (*host_active_ == 0) break;
     }
+  }
+  if (prof && run > 0) {
+    // Every launch of the loop counted all B energies, but an energy stops at its convergence
+    // check (the products of later iterations skip it): energy b ran iterations 1 .. iters[b].
+    std::vector<int32_t> its(B_);
+    RGF_HIP(hipMemcpyAsync(its.data(), iters_, sizeof(int32_t) * B_, hipMemcpyDeviceToHost, st_));
+    RGF_HIP(hipStreamSynchronize(st_));
+    double ran = 0.0;
+    for (int32_t n : its) ran += std::min<int32_t>(std::max<int32_t>(n, 0), run);
+    const double counted = profile_thread_flops() - flops0;
+    profile_uncount_flops(PC_LEAD, counted * (1.0 - ran / ((double)run * B_)));
   }
 }
 

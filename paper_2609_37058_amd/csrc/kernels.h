@@ -99,6 +99,11 @@ void profile_launch_end(hipStream_t st, int cls, double flops);
 // given the calling thread's site and phase
 int profile_class(int role, int rows);
 int profile_panel_class();
+// Flops counted so far by the calling thread's launches (a running total while profiling), and
+// the removal of counted flops from a class: a launch counts every energy of its batch, so work
+// that energies skip in-kernel (a converged decimation) is taken back out afterwards.
+double profile_thread_flops();
+void profile_uncount_flops(int cls, double flops);
 // Scope guards (thread-local): products launched inside belong to `cls` (unless they are
 // role-1 or 64-row products), or, inside a lead scope, to the decimation and self-energies.
 struct ProfSite {

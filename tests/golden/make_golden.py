@@ -3,7 +3,7 @@
 Calls only ``oracle`` and ``synth`` (no GPU code).  Usage:
     python tests/golden/make_golden.py [--jobs N] [name ...]
 with names from c2 c3 c4 c4_bloch kmesh_m256 bias_m1024 kpm_m1024
-(default: all; c4_bloch reads c4.json).
+(default: all; c4_bloch and c4_rethread read c4.json).
 
 Transmission configs (tests/golden/<cfg>.json): grid indices, energies and
 the FP64 oracle's T_LR (block-Thomas solve, Sancho-Rubio leads), the
@@ -20,6 +20,10 @@ imaginary part of the trace and the decimation iteration counts.
         only reproducible to the spread of such constructions (the tests add
         it to the bar).  One 2M x 2M eigenproblem per energy, about 14 CPU-
         minutes at M = 1024; --jobs N runs N energies at once.
+  c4_rethread -- add to c4.json, for every sampled energy, T from the same
+        construction as T with the oracle's BLAS limited to 4 threads: a
+        different summation order, so the difference from T is the oracle's
+        own FP64 reproducibility there (the tests add it to the bar too).
 The forms beyond T(E) at the shapes the benchmark times, reduced in the
 layer count only:
   kmesh_m256 -- the benchmark's k-mesh recipe (decay-weighted layers of
@@ -106,6 +110,33 @@ def bloch_spread(name, jobs):
     write(name, out)
 
 
+def _rethread_T(args):
+    name, i, threads = args
+    from threadpoolctl import threadpool_limits
+    cfg = CONFIGS[name]()
+    with threadpool_limits(limits=threads):
+        T = oracle.transmission(cfg.device, cfg.energies[i:i + 1], cfg.eta, method="thomas")
+    return i, float(np.real(T[0]))
+
+
+def rethread_spread(name, jobs, threads=4):
+    """T at every sampled energy of an existing golden from the same oracle construction with its
+    BLAS limited to `threads` threads (see the header)."""
+    import concurrent.futures as cf
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path) as f:
+        out = json.load(f)
+    idx = out["indices"]
+    t0 = time.time()
+    with cf.ProcessPoolExecutor(max_workers=jobs) as ex:
+        res = dict(ex.map(_rethread_T, [(name, i, threads) for i in idx]))
+    out["rethread_indices"] = idx
+    out["T_rethread"] = [res[i] for i in idx]
+    out["rethread_oracle"] = f"{out['oracle']}, BLAS limited to {threads} threads"
+    out["rethread_cpu_seconds"] = round(time.time() - t0, 1)
+    write(name, out)
+
+
 def write(name, out):
     path = os.path.join(HERE, f"{name}.json")
     with open(path, "w") as f:
@@ -168,6 +199,8 @@ def main(names, jobs=1):
             transmission_config(name)
         elif name.endswith("_bloch") and name[:-6] in SAMPLES:
             bloch_spread(name[:-6], jobs)
+        elif name.endswith("_rethread") and name[:-9] in SAMPLES:
+            rethread_spread(name[:-9], jobs)
         elif name == "kmesh_m256":
             cfg, images, R, kk, w, E = kmesh_device()
             T, Tk = okm.transmission_kmesh(images, R, kk, w, E, cfg.eta, method="thomas")
@@ -199,4 +232,4 @@ if __name__ == "__main__":
         k = argv.index("--jobs")
         jobs = int(argv[k + 1])
         del argv[k:k + 2]
-    main(argv or ["kpm_m1024", "bias_m1024", "kmesh_m256", "c2", "c3", "c4", "c4_bloch"], jobs)
+    main(argv or ["kpm_m1024", "bias_m1024", "kmesh_m256", "c2", "c3", "c4", "c4_bloch", "c4_rethread"], jobs)

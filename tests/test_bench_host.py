@@ -37,6 +37,16 @@ def test_class_rooflines_mixed_uses_the_fp32_peak_for_fp32_parts():
     assert out["solve"]["peak_tflops"] == 157.3 and out["lead"]["peak_tflops"] == 78.6
 
 
+def test_decimation_class_reports_executed_flops_but_no_rate():
+    """A decimation launch counts every energy of its batch while converged energies skip it, so
+    the class keeps its (corrected) flop total for the whole-step count but reports no rate."""
+    cls = {"sweep": _cls(10.0, 1e12), "lead": _cls(10.0, 2e12, flops=5e12)}
+    out = bench.class_rooflines(cls, "fp64")
+    assert out["lead"]["achieved_tflops"] is None and out["lead"]["frac"] is None
+    assert out["lead"]["flops"] == 5e12 and "flops_note" in out["lead"]
+    assert out["sweep"]["frac"] is not None
+
+
 def test_measured_traffic_reads_the_summary_and_checks_the_digest(monkeypatch):
     kv = {}
     with open(bench.TRAFFIC_SUMMARY) as f:

@@ -161,3 +161,32 @@ def test_profile_samples_every_nth_launch(lib):
     assert counts[1] > 0
     for every in (3, 4):
         assert counts[every] == -(-counts[1] // every)
+
+
+def test_decimation_flops_count_the_iterations_each_energy_ran(lib, monkeypatch):
+    """With the class profile on, the decimation class counts only the iterations each energy ran
+    (later launches skip a converged energy in-kernel).  Energies far outside the lead's spectrum
+    converge in a few iterations, band energies at eta = 1e-6 need about twenty; a count of whole
+    launches would charge the former the latter's iterations whenever both share a call.  The
+    executed work is per energy, so a call of both sets counts the sum of the two sets' calls."""
+    monkeypatch.setenv("RGF_LANES", "1")
+    dev = synth.random_small_device(3, 300, seed=43)
+    bound = np.linalg.norm(dev.left.H00, 2) + 2.0 * np.linalg.norm(dev.left.H01, 2)
+    gap = np.array([3.0 * bound, 3.5 * bound])
+    band = np.array([0.0, 0.1 * bound])
+    dt = stage(dev)
+
+    def lead_flops(E):
+        lib.profile_classes(True, 1)
+        lib.profile_read_classes()
+        T, info = _single(lib, dt, E, 1e-6)
+        c = lib.profile_read_classes()["lead"]
+        lib.profile_classes(False)
+        assert np.all(info == 0)
+        return c["flops"]
+
+    f_gap, f_band = lead_flops(gap), lead_flops(band)
+    f_both = lead_flops(np.concatenate([gap, band]))
+    log(f"[profile] decimation flops: gap {f_gap:.4e}, band {f_band:.4e}, both {f_both:.4e}")
+    assert 0 < f_gap < f_band
+    assert abs(f_both - (f_gap + f_band)) <= 1e-9 * f_both
