@@ -3,7 +3,7 @@
 Calls only ``oracle`` and ``synth`` (no GPU code).  Usage:
     python tests/golden/make_golden.py [--jobs N] [name ...]
 with names from c2 c3 c4 c4_bloch kmesh_m256 bias_m1024 kpm_m1024
-(default: all; c4_bloch and c4_rethread read c4.json).
+(default: all; c4_bloch, c4_rethread and c4_scaled read c4.json).
 
 Transmission configs (tests/golden/<cfg>.json): grid indices, energies and
 the FP64 oracle's T_LR (block-Thomas solve, Sancho-Rubio leads), the
@@ -23,7 +23,13 @@ imaginary part of the trace and the decimation iteration counts.
   c4_rethread -- add to c4.json, for every sampled energy, T from the same
         construction as T with the oracle's BLAS limited to 4 threads: a
         different summation order, so the difference from T is the oracle's
-        own FP64 reproducibility there (the tests add it to the bar too).
+        own FP64 reproducibility there (the tests add it to the bar too; on
+        this machine it came out bitwise equal to T).
+  c4_scaled -- add to c4.json, for every sampled energy, T of the device and
+        electrodes with every H and S block times 3: exactly T in exact
+        arithmetic (z 3S - 3H = 3 (zS - H) scales G by 1/3 and Sigma, Gamma by
+        3), with every rounding changed, so its difference from T is T's FP64
+        sensitivity to rounding there (the tests add it to the bar too).
 The forms beyond T(E) at the shapes the benchmark times, reduced in the
 layer count only:
   kmesh_m256 -- the benchmark's k-mesh recipe (decay-weighted layers of
@@ -137,6 +143,51 @@ def rethread_spread(name, jobs, threads=4):
     write(name, out)
 
 
+def scaled_device(dev, c):
+    """Every block of the device and its electrodes times c.  Then z cS - cH = c (zS - H), so G
+    becomes G / c and Sigma, Gamma become c Sigma, c Gamma: T = Tr[Gamma_L G Gamma_R G^+] is
+    unchanged in exact arithmetic, while every rounding of the computation changes."""
+    import dataclasses
+    sc = lambda L: synth.Lead(c * L.H00, c * L.H01, c * L.S00, c * L.S01)
+    if dev.base is not None and dev._hd is None:
+        return dataclasses.replace(dev, left=sc(dev.left), right=sc(dev.right), base=sc(dev.base),
+                                   shifts={k: c * v for k, v in dev.shifts.items()})
+    N = dev.N
+    return synth.device_from_blocks([c * dev.Hd(i) for i in range(N)], [c * dev.Hu(i) for i in range(N - 1)],
+                                    [c * dev.Sd(i) for i in range(N)], [c * dev.Su(i) for i in range(N - 1)],
+                                    sc(dev.left), sc(dev.right), name=dev.name + "-scaled")
+
+
+SCALE = 3.0
+
+
+def _scaled_T(args):
+    name, i = args
+    from threadpoolctl import threadpool_limits
+    cfg = CONFIGS[name]()
+    with threadpool_limits(limits=4):
+        T = oracle.transmission(scaled_device(cfg.device, SCALE), cfg.energies[i:i + 1], cfg.eta, method="thomas")
+    return i, float(np.real(T[0]))
+
+
+def scaled_spread(name, jobs):
+    """T at every sampled energy of an existing golden from the device and electrodes scaled by
+    SCALE (see the header)."""
+    import concurrent.futures as cf
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path) as f:
+        out = json.load(f)
+    idx = out["indices"]
+    t0 = time.time()
+    with cf.ProcessPoolExecutor(max_workers=jobs) as ex:
+        res = dict(ex.map(_scaled_T, [(name, i) for i in idx]))
+    out["scaled_indices"] = idx
+    out["T_scaled"] = [res[i] for i in idx]
+    out["scaled_oracle"] = f"{out['oracle']}, every H and S block (device and electrodes) times {SCALE}"
+    out["scaled_cpu_seconds"] = round(time.time() - t0, 1)
+    write(name, out)
+
+
 def write(name, out):
     path = os.path.join(HERE, f"{name}.json")
     with open(path, "w") as f:
@@ -201,6 +252,8 @@ def main(names, jobs=1):
             bloch_spread(name[:-6], jobs)
         elif name.endswith("_rethread") and name[:-9] in SAMPLES:
             rethread_spread(name[:-9], jobs)
+        elif name.endswith("_scaled") and name[:-7] in SAMPLES:
+            scaled_spread(name[:-7], jobs)
         elif name == "kmesh_m256":
             cfg, images, R, kk, w, E = kmesh_device()
             T, Tk = okm.transmission_kmesh(images, R, kk, w, E, cfg.eta, method="thomas")
@@ -232,4 +285,5 @@ if __name__ == "__main__":
         k = argv.index("--jobs")
         jobs = int(argv[k + 1])
         del argv[k:k + 2]
-    main(argv or ["kpm_m1024", "bias_m1024", "kmesh_m256", "c2", "c3", "c4", "c4_bloch", "c4_rethread"], jobs)
+    main(argv or ["kpm_m1024", "bias_m1024", "kmesh_m256", "c2", "c3", "c4", "c4_bloch", "c4_rethread", "c4_scaled"],
+         jobs)
