@@ -128,7 +128,8 @@ def c4_dev():
 C4_MISS = (469,)
 C4_MISS_REASON = ("at the C4 grid point E = 1.6712 the FP64 path gives T 2.0e-8 relative below the oracle, while "
                   "the oracle's own constructions (Bloch-mode leads, every block scaled by 3, other BLAS "
-                  "threading) agree with it within 2.5e-9, so the bar there is 1.5e-8: not met")
+                  "threading) agree with it within 2.5e-9, so the bar there is 1.5e-8: not met; the loss is in "
+                  "the decimation's triangular solves, which apply explicitly inverted diagonal blocks")
 
 
 @pytest.fixture(scope="module")
