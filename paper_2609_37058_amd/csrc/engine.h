@@ -95,7 +95,8 @@ class Engine {
   // `fusable`: the fused Gauss-Jordan kernel may serve this solve (the sweep's); the decimation
   // iterates on blocks whose conditioning degrades, where LU with substitution keeps more digits.
   MatRef factor_solve(z64* T, z64* Y, int64_t yld, int64_t ybs, int nrhs, std::vector<FillArgs> rhs,
-                      const int32_t* skip, int32_t code, int lp, int tp, int tile, bool fusable);
+                      const int32_t* skip, int32_t code, int lp, int tp, int tile, bool fusable,
+                      bool exact_u = false);
   double gemm(GemmArgs g, int prec, bool timed);
   void ldos_pass(const rgf_device& d, z64* store, const double* twos, z64* sblk, bool forward, double* dos,
                  double* inj);

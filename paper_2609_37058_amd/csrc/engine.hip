@@ -143,7 +143,8 @@ MatRef Engine::mref(z64* p, int64_t ld, int64_t bstride, const int32_t* ridx) co
 }
 
 MatRef Engine::factor_solve(z64* T, z64* Y, int64_t yld, int64_t ybs, int nrhs, std::vector<FillArgs> rhs,
-                            const int32_t* skip, int32_t code, int lp, int tp, int tile, bool fusable) {
+                            const int32_t* skip, int32_t code, int lp, int tp, int tile, bool fusable,
+                            bool exact_u) {
   if (fused_ && fusable) {
     for (FillArgs& f : rhs) launch_fill(f, B_, st_);
     GjArgs a;
@@ -161,7 +162,9 @@ MatRef Engine::factor_solve(z64* T, z64* Y, int64_t yld, int64_t ybs, int nrhs, 
     launch_gj(a, B_, st_);
     return mref(Y, yld, ybs, lu_.perm);
   }
-  lu_factor(lu_, T, MM_, Mp_, B_, skip, code, lp, tile, st_);
+  LuBufs lu = lu_;
+  lu.exact_u = exact_u;
+  lu_factor(lu, T, MM_, Mp_, B_, skip, code, lp, tile, st_);
   for (FillArgs& f : rhs) {  // the right-hand sides in pivot order
     if (f.kind == FILL_MAT) {
       f.src.rowidx = lu_.perm;
@@ -172,7 +175,7 @@ MatRef Engine::factor_solve(z64* T, z64* Y, int64_t yld, int64_t ybs, int nrhs, 
     }
     launch_fill(f, B_, st_);
   }
-  lu_solve(lu_, T, MM_, Mp_, Y, ybs, nrhs, B_, skip, tp, tile, st_);
+  lu_solve(lu, T, MM_, Mp_, Y, ybs, nrhs, B_, skip, tp, tile, st_);
   return mref(Y, yld, ybs);
 }
 
@@ -221,8 +224,9 @@ void Engine::decimate(const rgf_lead& lead, int32_t* done, bool left) {
     FillArgs rb = ra;
     rb.dst = mref(Ysr_ + Mp, 2 * Mp, 2 * MM_);
     rb.src = mref(AB_ + MM_, Mp, 2 * MM_);
+    // near band extrema eps is ill-conditioned: the solves substitute with U's diagonal blocks
     const MatRef Xab = factor_solve(Tsr_, Ysr_, 2 * Mp, 2 * MM_, 2 * Mp, {ra, rb}, done, SING_LEAD, PREC_F64,
-                                    PREC_F64, tile, false);
+                                    PREC_F64, tile, false, true);
     // the four products [alpha; beta] [Xa Xb]
     GemmArgs g = gemm_args(2 * Mp, 2 * Mp, Mp, B_);
     g.A = mref(AB_, Mp, 2 * MM_);
@@ -274,7 +278,7 @@ void Engine::self_energy(const rgf_lead& lead, bool left, z64* out) {
   const double* El = left ? EL_ : ER_;
   f.f = gform(form(lead.H01, lead.S01, M_, /*conj_t=*/!left, false, El, eta_));
   const MatRef X =
-      factor_solve(Tsr_, Ysr_, Mp, 2 * MM_, Mp, {f}, nullptr, SING_LEAD, PREC_F64, PREC_F64, tile, false);
+      factor_solve(Tsr_, Ysr_, Mp, 2 * MM_, Mp, {f}, nullptr, SING_LEAD, PREC_F64, PREC_F64, tile, false, true);
   GemmArgs g = gemm_args(Mp, Mp, Mp, B_);
   g.a_kind = SRC_FORM;
   g.Af = gform(form(lead.H01, lead.S01, M_, /*conj_t=*/left, false, El, eta_));

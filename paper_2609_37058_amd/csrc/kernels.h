@@ -144,6 +144,7 @@ struct LuPanelArgs {
   int32_t* sing;    // per batch: first singular event code (0 = none)
   int32_t sing_code;
   BatchCtl ctl;
+  int u_plain = 0;  // 1: uinv receives the diagonal blocks of U themselves, not their inverses
 };
 void launch_lu_panel(const LuPanelArgs& a, int batch, hipStream_t st);
 
@@ -158,6 +159,10 @@ struct LuBufs {
   uint8_t* flags;
   int32_t* sing;
   int32_t* cand2 = nullptr;
+  // Exact diagonal blocks of U: the factorisation keeps U's 64 x 64 diagonal blocks (in uinv's
+  // storage) and the solve substitutes with them instead of applying their explicit inverses,
+  // which lose digits when U is ill-conditioned (the lead decimation near band extrema).
+  bool exact_u = false;
 };
 // Factor T (Mp x Mp per batch, batch stride bs) in place.  Block products
 // (trailing updates) run in `prec`; pivoting and diagonal blocks in FP64.

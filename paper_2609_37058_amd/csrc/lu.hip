@@ -352,7 +352,11 @@ __global__ __launch_bounds__(512) void lu_panel_kernel(LuPanelArgs a) {
   z64* li = a.linv + (int64_t)b * a.inv_bs + (int64_t)(k0 / NB) * NB * NB;
   z64* ui = a.uinv + (int64_t)b * a.inv_bs + (int64_t)(k0 / NB) * NB * NB;
   tri_invert<true>(Lw, dinv, li, tid, nt);
-  tri_invert<false>(U, dinv, ui, tid, nt);
+  if (a.u_plain) {
+    for (int e = tid; e < NB * NB; e += nt) ui[e] = U[e];
+  } else {
+    tri_invert<false>(U, dinv, ui, tid, nt);
+  }
   if (tid < NB) a.perm[(int64_t)b * a.perm_bs + k0 + tid] = piv[tid];
   for (int r = tid; r < Mp; r += nt) gflags[r] = fl[r] ? 1 : 0;
   if (tid == 0 && sh_sing && a.sing && a.sing[b] == 0) a.sing[b] = a.sing_code;

@@ -80,6 +80,7 @@ void lu_factor(const LuBufs& g, z64* T, int64_t bs, int Mp, int batch, const int
     pa.sing = g.sing;
     pa.sing_code = code;
     pa.ctl.skip = skip;
+    pa.u_plain = g.exact_u ? 1 : 0;
     launch_lu_panel(pa, batch, st);
   };
   // B[piv(k0), c0 : c0 + ncols] = L11(k0)^-1 B[piv(k0), ...], in place (one row tile)
@@ -167,6 +168,48 @@ static void update(GemmArgs base, z64* Yrows, int rows, const MatRef& A, z64* Ys
   launch_gemm(o, prec, tile, st, 0);
 }
 
+// Y_rows <- U^-1 Y_rows in place for one 64 x 64 upper-triangular block U (row-major, batch
+// stride u_bs) by back substitution: one right-hand-side column per thread.  U is staged in
+// LDS (read as a broadcast), the thread's 64 unknowns in an LDS column of their own; each dot
+// product runs as four partial sums, so the chain of dependent multiply-adds is a quarter long.
+__global__ __launch_bounds__(64) void usolve_kernel(const z64* U, int64_t u_bs, z64* Y, int64_t ybs, int nrhs,
+                                                    const int32_t* skip) {
+  __shared__ z64 u[LU_NB * LU_NB];
+  __shared__ z64 x[LU_NB * 64];
+  const int b = blockIdx.y;
+  if (skip && skip[b]) return;  // uniform over the workgroup
+  const int t = threadIdx.x;
+  const z64* Ub = U + (int64_t)b * u_bs;
+  for (int e = t; e < LU_NB * LU_NB; e += 64) u[e] = Ub[e];
+  const int c = blockIdx.x * 64 + t;
+  const bool act = c < nrhs;
+  z64* y = Y + (int64_t)b * ybs + (act ? c : 0);
+  for (int i = 0; i < LU_NB; ++i) x[i * 64 + t] = act ? y[(int64_t)i * nrhs] : zmake(0.0, 0.0);
+  __syncthreads();  // u complete; each thread touches only its own column of x
+  for (int i = LU_NB - 1; i >= 0; --i) {
+    z64 s0 = x[i * 64 + t], s1 = zmake(0.0, 0.0), s2 = s1, s3 = s1;
+    const z64* ui = u + i * LU_NB;
+    int j = i + 1;
+    for (; j + 3 < LU_NB; j += 4) {
+      s0 = zfms(ui[j], x[j * 64 + t], s0);
+      s1 = zfms(ui[j + 1], x[(j + 1) * 64 + t], s1);
+      s2 = zfms(ui[j + 2], x[(j + 2) * 64 + t], s2);
+      s3 = zfms(ui[j + 3], x[(j + 3) * 64 + t], s3);
+    }
+    for (; j < LU_NB; ++j) s0 = zfms(ui[j], x[j * 64 + t], s0);
+    x[i * 64 + t] = zmul(zadd(zadd(s0, s1), zadd(s2, s3)), zinv(ui[i]));
+  }
+  if (act)
+    for (int i = 0; i < LU_NB; ++i) y[(int64_t)i * nrhs] = x[i * 64 + t];
+}
+
+static void usolve(z64* Yrows, const z64* U, int64_t u_bs, int64_t ybs, int nrhs, int batch, const int32_t* skip,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(usolve_kernel, dim3((unsigned)((nrhs + 63) / 64), (unsigned)batch), dim3(64), 0, st, U, u_bs,
+                     Yrows, ybs, nrhs, skip);
+  RGF_HIP(hipGetLastError());
+}
+
 // Y_rows = D Y_rows in place (64 rows: one row tile, so each workgroup owns its columns)
 static void diag(GemmArgs base, z64* Yrows, const z64* D, int64_t inv_bs, int64_t ybs, int nrhs, int prec, int tile,
                  hipStream_t st) {
@@ -210,10 +253,12 @@ void lu_solve(const LuBufs& g, z64* T, int64_t bs, int Mp, z64* Y, int64_t ybs, 
     const int q = p - two + 1;  // first panel of this block
     const int rend = (p + 1) * LU_NB;
     update(base, Yr(q), two * LU_NB, Lrows(q, rend), Yr(p + 1), Mp - rend, ybs, nrhs, prec, tile, st);
-    diag(base, Yr(p), Uinv(p), inv_bs, ybs, nrhs, prec, tile, st);
+    if (g.exact_u) usolve(Yr(p), Uinv(p), inv_bs, ybs, nrhs, batch, skip, st);
+    else diag(base, Yr(p), Uinv(p), inv_bs, ybs, nrhs, prec, tile, st);
     if (two == 2) {
       update(base, Yr(q), LU_NB, Lrows(q, p * LU_NB), Yr(p), LU_NB, ybs, nrhs, prec, tile, st);
-      diag(base, Yr(q), Uinv(q), inv_bs, ybs, nrhs, prec, tile, st);
+      if (g.exact_u) usolve(Yr(q), Uinv(q), inv_bs, ybs, nrhs, batch, skip, st);
+      else diag(base, Yr(q), Uinv(q), inv_bs, ybs, nrhs, prec, tile, st);
     }
     p -= two;
   }

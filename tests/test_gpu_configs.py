@@ -18,9 +18,9 @@ sharp features, T is reproducible in FP64 only to that spread (at the C4
 grid point E = 1.6712 the decimation and Bloch-mode constructions of Sigma
 differ by 2.7e-8 and 7.6e-8 relative), and a correct GPU result can lie that
 far from any one oracle value; elsewhere the spread is far below the bar.
-At that grid point the oracle's constructions agree within 2.5e-9 but the
-FP64 path is 2.0e-8 from them, above its bar of 1.5e-8: that sample is a
-strict expected failure of its own, and the other 15 C4 samples hold the bar.
+At that grid point the oracle's constructions agree within 2.5e-9; the FP64
+path's decimation substitutes with the diagonal blocks of U there (explicit
+inverses of those blocks had put T 2.0e-8 off).
 Mixed bar: |T_gpu - T_oracle| <= 1e-4.  The FP32 matrix-core form does not
 reach it on these workloads (FP32 accumulation leaves ~1e-6 relative error
 per product and the near-singular layer blocks at eta = 1e-6 amplify it), so
@@ -54,7 +54,7 @@ def golden(name):
         return json.load(f)
 
 
-def _compare(tag, T, g, precision, keep=None):
+def _compare(tag, T, g, precision):
     ref = np.array(g["T"])
     err = np.abs(T - ref)
     # the oracle's own FP64 spread at each sample: T from Bloch-mode leads, from the same
@@ -65,9 +65,6 @@ def _compare(tag, T, g, precision, keep=None):
         for i, t in zip(g.get(f"{kind}_indices", []), g.get(f"T_{kind}", [])):
             spread[pos[i]] = max(spread[pos[i]], abs(ref[pos[i]] - t))
     E = np.array(g["E"])
-    if keep is not None:  # the samples this comparison covers
-        keep = np.asarray(keep, bool)
-        ref, err, spread, E = ref[keep], err[keep], spread[keep], E[keep]
     if precision == "fp64":
         ok = err <= FP64_RTOL * np.abs(ref) + FP64_ATOL + 2.0 * spread
     else:
@@ -123,15 +120,6 @@ def c4_dev():
     torch.cuda.empty_cache()
 
 
-# The C4 sample where the FP64 path misses its bar (grid index 469, E = 1.6712, where the two
-# oracle constructions of Sigma differ most): checked on its own below, as an expected failure.
-C4_MISS = (469,)
-C4_MISS_REASON = ("at the C4 grid point E = 1.6712 the FP64 path gives T 2.0e-8 relative below the oracle, while "
-                  "the oracle's own constructions (Bloch-mode leads, every block scaled by 3, other BLAS "
-                  "threading) agree with it within 2.5e-9, so the bar there is 1.5e-8: not met; the loss is in "
-                  "the decimation's triangular solves, which apply explicitly inverted diagonal blocks")
-
-
 @pytest.fixture(scope="module")
 def c4_runs():
     return {}
@@ -157,22 +145,12 @@ def _c4_result(lib, c4_dev, c4_runs, precision):
 
 @_precision_param()
 def test_c4_sampled(lib, c4_dev, c4_runs, precision):
-    """400 layers, M = 1024 (25 GiB of blocks): the sampled energies inside a 256-energy call on
-    one energy lane, the benchmark's step; in FP64 all but the one sample checked below."""
+    """400 layers, M = 1024 (25 GiB of blocks): the 16 sampled energies inside a 256-energy call
+    on one energy lane, the benchmark's step."""
     g = golden("c4")
     T, info = _c4_result(lib, c4_dev, c4_runs, precision)
     assert np.all(info == 0)
-    keep = [i not in C4_MISS for i in g["indices"]] if precision == "fp64" else None
-    _compare("c4", T, g, precision, keep)
-
-
-@pytest.mark.xfail(strict=True, reason=C4_MISS_REASON)
-def test_c4_fp64_at_e_1_6712(lib, c4_dev, c4_runs):
-    """The FP64 bar at the C4 sample E = 1.6712, from the same call as test_c4_sampled."""
-    g = golden("c4")
-    T, info = _c4_result(lib, c4_dev, c4_runs, "fp64")
-    assert np.all(info == 0)
-    _compare("c4 E = 1.6712", T, g, "fp64", [i in C4_MISS for i in g["indices"]])
+    _compare("c4", T, g, precision)
 
 
 def test_batch_invariance_and_determinism(lib, c2_dev):
