@@ -754,7 +754,8 @@ def main():
         sr_ms = ev0.elapsed_time(ev1)
         out["parts_ms_per_step"] = {"self_energy_alone": sr_ms,
                                     "sweep_and_trace": results["fp64"]["ms_per_step"] - sr_ms}
-    if dom == "sweep" and sw["launches"] and left() > tail_s:
+    # about 2 s of device time; the CPU baseline after it caps its own time to what is left
+    if dom == "sweep" and sw["launches"] and left() > 10.0 + (0.0 if args.no_cpu_baseline else args.cpu_seconds):
         # With several energy lanes their kernels run at the same time, so a launch's event-timed
         # duration above includes device time shared with the other lanes' kernels.  The same
         # launches alone on the device give the kernel's own rate.
