@@ -22,6 +22,7 @@ static int kt_guard(F&& f) {
 
 // Whether the harness's LU runs look ahead (a second candidate list, see lu_factor).
 static int g_kt_lookahead = 1;
+static int g_kt_exact_u = 0;
 
 extern "C" {
 
@@ -29,6 +30,14 @@ extern "C" {
 int rgf_ktest_set_lookahead(int on) {
   const int prev = g_kt_lookahead;
   g_kt_lookahead = on ? 1 : 0;
+  return prev;
+}
+
+// Solve with U's diagonal blocks by substitution (1) or with their explicit inverses (0, the
+// default) in the harness's LU; returns the previous setting.
+int rgf_ktest_set_exact_u(int on) {
+  const int prev = g_kt_exact_u;
+  g_kt_exact_u = on ? 1 : 0;
   return prev;
 }
 
@@ -70,6 +79,7 @@ int rgf_ktest_lu(int prec, int Mp, int nrhs, int batch, void* B, const void* RHS
     RGF_HIP(hipMalloc((void**)&g.flags, batch * Mp));
     RGF_HIP(hipMalloc((void**)&g.sing, sizeof(int32_t) * batch));
     RGF_HIP(hipMemset(g.sing, 0, sizeof(int32_t) * batch));
+    g.exact_u = g_kt_exact_u != 0;
     const int64_t bs = (int64_t)Mp * Mp, ybs = (int64_t)Mp * nrhs;
     lu_factor(g, (z64*)B, bs, Mp, batch, nullptr, 1, prec, 128, nullptr);
     FillArgs f;

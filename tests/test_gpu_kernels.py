@@ -33,6 +33,7 @@ def kt():
     lib.rgf_ktest_gj.argtypes = [C.c_int] * 3 + [C.c_void_p] * 6
     lib.rgf_ktest_set_small_k.argtypes = [C.c_int]
     lib.rgf_ktest_set_lookahead.argtypes = [C.c_int]
+    lib.rgf_ktest_set_exact_u.argtypes = [C.c_int]
     return lib
 
 
@@ -154,6 +155,49 @@ def test_lu_solve_matches_numpy_solve(kt, prec, Mp, nrhs, batch):
     assert np.all(sing == 0)
     # FP32 trailing updates and solves: the error grows with the order of these row-scaled random systems
     assert err < (1e-11 if prec == 0 else 1e-3 * max(1.0, Mp / 512))
+
+
+@pytest.mark.parametrize("Mp,nrhs,batch,graded", [(128, 128, 2, False), (512, 320, 2, False), (1024, 128, 1, False),
+                                                  (256, 256, 2, True), (1024, 64, 1, True)])
+def test_lu_solve_with_exact_u_blocks(kt, Mp, nrhs, batch, graded):
+    """The decimation's solve: the panel kernel keeps U's 64 x 64 diagonal blocks and the solve
+    back-substitutes with them instead of applying their inverses.  On row-scaled random systems
+    it matches numpy's solve like the default path; on column-graded ones (columns scaled over
+    twelve decades, so U's diagonal blocks are ill-conditioned) its backward error stays at
+    rounding level."""
+    import torch
+    rng = np.random.default_rng(7 * Mp + nrhs)
+    Bm = _rand(rng, (batch, Mp, Mp))
+    if graded:
+        Bm *= 10.0 ** rng.uniform(-12, 0, size=(batch, 1, Mp))
+    else:
+        Bm *= np.exp(rng.uniform(-3, 3, size=(batch, Mp, 1)))
+    R = _rand(rng, (batch, Mp, nrhs))
+    tr = torch.as_tensor(np.ascontiguousarray(R)).cuda()
+    tb = torch.as_tensor(np.ascontiguousarray(Bm)).cuda()
+    X = torch.zeros((batch, Mp, nrhs), dtype=torch.complex128, device="cuda")
+    perm = np.zeros((batch, Mp), np.int32)
+    sing = np.zeros(batch, np.int32)
+    log(f"[kernel] lu exact U blocks Mp={Mp} nrhs={nrhs} b={batch} graded={graded}")
+    prev = kt.rgf_ktest_set_exact_u(1)
+    try:
+        assert kt.rgf_ktest_lu(0, Mp, nrhs, batch, tb.data_ptr(), tr.data_ptr(), X.data_ptr(), perm.ctypes.data,
+                               sing.ctypes.data) == 0
+    finally:
+        kt.rgf_ktest_set_exact_u(prev)
+    got = X.cpu().numpy()
+    assert np.all(sing == 0)
+    if graded:
+        res = np.einsum("bij,bjk->bik", Bm, got) - R
+        back = max(np.linalg.norm(res[b]) / (np.linalg.norm(Bm[b]) * np.linalg.norm(got[b]) + np.linalg.norm(R[b]))
+                   for b in range(batch))
+        log(f"[kernel] lu exact U blocks backward error {back:.2e}")
+        assert back < 1e-13
+    else:
+        ref = np.linalg.solve(Bm, R)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        log(f"[kernel] lu exact U blocks rel err {err:.2e}")
+        assert err < 1e-11
 
 
 @pytest.mark.parametrize("M,Mp,batch,groups,pad", [(64, 64, 1, 1, 0), (100, 128, 13, 1, 0), (130, 192, 9, 3, 1),
