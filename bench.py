@@ -735,7 +735,7 @@ def main():
         },
         "convention_40M3": {
             "tflops": conv, "frac_of_fp64_peak": conv / FP64_MFMA_PEAK_TFLOPS,
-            "note": "40 M^3 real flops per point-layer: the survey's count for the inverse-based RGF, a "
+            "note": "40 M^3 real flops per point-layer: the usual count for the inverse-based RGF, a "
                     "convention for comparing point-layer rates, not the work this solve-based sweep executes",
         },
         "nonzero_info": head["nonzero_info"],
